@@ -1,0 +1,94 @@
+/* CPU oracle for the spin-dependent hot-electron particle-in-cell step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow FP64 reference written from
+ * Nenno, Rethfeld and Schneider, arXiv:1807.04733, Sec. III.A (Eqs. 10-19).  Only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg may load it.  It
+ * shares no code, header or table generator with the device library.
+ *
+ * Units: z in nm, t in fs, velocities in nm/fs, energies as uint32 with LSB 2^-30 eV.
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_C_INJECTED = 0, ORC_C_EV_EE, ORC_C_EV_EL, ORC_C_SPAWNED, ORC_C_ABSORBED,
+  ORC_C_SEC_ABSORBED, ORC_C_TRANSMIT, ORC_C_REFL_IF, ORC_C_REFL_SURF, ORC_C_ALIVE, ORC_C_E_ABSORBED,
+  ORC_NCOUNTERS
+};
+
+typedef struct {
+  int32_t n_layers, n_channels, n_ttables, t_entries;
+  const double*  z_bound;     /* [L+1] */
+  const int32_t* ch_of;       /* [L][2] channel of (layer, global spin) */
+  const double*  v;           /* [C] nm/fs */
+  const double*  inv_tau0;    /* [C] 1/fs */
+  const double*  inv_tau_el;  /* [L] 1/fs */
+  const double*  P0;          /* [L] */
+  const double*  T;           /* [NT][TE] */
+  const int32_t* tt_of;       /* [L-1][2][2] */
+  double T_scale;
+  double src_z_lo, src_z_hi, src_lambda, src_cd, src_up_frac;
+  uint32_t src_e_lo[2], src_e_span[2];
+  const int64_t* sched;       /* [n_steps] */
+  uint64_t root_offset;
+  int32_t nz;
+  double inv_dz;
+} orc_instance;
+
+typedef struct {
+  int32_t n_instances;
+  const orc_instance* inst;
+  uint64_t seed;
+  double dt;
+  int32_t n_steps;
+  int32_t tau_exp;            /* 0: tau = tau0, 2: tau = tau0 (1 eV/E)^2 */
+  uint32_t e_min_fx;
+  int32_t secondaries;
+  int32_t state_fp64;         /* 0: positions/directions stored as binary32 */
+  int32_t n_ebins;
+  const uint32_t* e_edges;    /* [n_ebins] lower edges */
+  int32_t dens_stride, cur_stride;
+  int64_t root_lo, root_hi;   /* simulate local roots in [lo, hi) of every instance; hi<0: all */
+  int32_t n_threads;          /* 0: OpenMP default */
+} orc_problem;
+
+typedef struct {
+  /* bins, flattened over instances in order: dens [n_dslots][nz][NE][2], cur [n_cslots][nz][2] */
+  uint64_t* dens;
+  int64_t*  cur;              /* fixed point, 2^-32 nm/fs per unit */
+  int64_t*  counters;         /* [n_steps][ORC_NCOUNTERS] */
+  /* optional per-particle records of every particle ever created (NULL to skip) */
+  int64_t   rec_cap;
+  int64_t   n_rec;            /* out */
+  uint64_t* rec_uid;
+  double*   rec_z;
+  double*   rec_mu;
+  uint32_t* rec_E;
+  int32_t*  rec_layer;
+  int32_t*  rec_spin;
+  int32_t*  rec_gen;
+  int32_t*  rec_dead;         /* step of absorption, -1 if alive at the end */
+  int32_t*  rec_inst;
+  int32_t*  rec_ev;           /* [4] per record: events, transmissions, reflections, spawns */
+  /* optional likelihood-ratio gradient (NULL to skip); see orc_run's gradient section */
+  const double* g_dens;       /* same layout as dens */
+  const double* g_cur;        /* same layout as cur (per unit of nm/fs) */
+  double*   grad;             /* [n_channels + n_ttables*t_entries] of instance 0's layout */
+  int32_t   grad_per_tree;    /* 0: causal score; 1: whole-tree return */
+} orc_output;
+
+/* Philox4x32 with 10 rounds (Salmon et al., SC'11), written from the published definition. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Run the whole problem; returns 0 on success, nonzero on invalid input or record overflow. */
+int orc_run(const orc_problem* p, orc_output* o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,402 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every test here runs on the CPU.  The checks are closed forms, exact discrete-time
+results, conservation laws, brute-force enumeration and an independent library
+implementation of the random-number generator, chosen so that a dropped term, a wrong
+sign or index, or a swapped operand in the oracle makes at least one of them fail.
+Statistical checks use 4 standard errors estimated from the sample itself.
+"""
+import ctypes as C
+import math
+import os
+import shutil
+import subprocess
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+INF = float("inf")
+
+
+def _run(oracle_lib, prob, **kw):
+    return oracle_lib.run(prob, **kw)
+
+
+def _primaries(rec):
+    return (rec["uid"] >> np.uint64(32)) == 0
+
+
+# --------------------------------------------------------------------------- Philox
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("no ROCm clang to build the rocRAND reference")
+    out = str(tmp_path_factory.mktemp("ref") / "librefphilox.so")
+    subprocess.run([clang, "-x", "hip", "--cuda-host-only", "-O2", "-fPIC", "-shared",
+                    "-I/opt/rocm/include", "-o", out,
+                    os.path.join(HERE, "pins", "rocrand_philox.cpp")], check=True)
+    return C.CDLL(out)
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_ref):
+    """The oracle's Philox4x32-10 equals rocRAND's engine on random counters and keys."""
+    rng = np.random.default_rng(7)
+    n = 2000
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:, 1] &= (1 << 30) - 1          # the reference's offset argument holds 4*(x|y<<32)
+    ctr[:8] = 0
+    ctr[1, 0] = 1
+    ctr[2, 3] = 0xFFFFFFFF
+    for key in ([0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0x243F6A88, 0x85A308D3]):
+        key = np.array(key, np.uint32)
+        ref = np.zeros((n, 4), np.uint32)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        rocrand_ref.ref_philox(p(ctr), p(key), p(ref), C.c_int64(n))
+        mine = np.array([oracle_lib.philox(c, key) for c in ctr])
+        assert np.array_equal(mine, ref)
+
+
+def test_philox_uniformity(oracle_lib):
+    """chi^2 of the top byte and balance of every bit over consecutive counters."""
+    words = np.array([oracle_lib.philox([i, 3, 5, 0x200], [11, 13]) for i in range(20000)],
+                     np.uint32).ravel()
+    counts = np.bincount(words >> 24, minlength=256)
+    exp = len(words) / 256
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert 160 < chi2 < 360                     # 255 dof, ~ +/- 4.5 sigma
+    bits = ((words[:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(0)
+    assert np.all(np.abs(bits - 0.5) < 4 * 0.5 / math.sqrt(len(words)))
+
+
+# --------------------------------------------------------------------------- A: ballistic
+def _fold(u, L):
+    """Reflecting-wall fold of an unfolded coordinate into [0, L]; returns (z, sign)."""
+    m = np.mod(u, 2 * L)
+    back = m > L
+    return np.where(back, 2 * L - m, m), np.where(back, -1.0, 1.0)
+
+
+def test_ballistic_homogeneous_closed_form(oracle_lib):
+    """tau -> infinity: the state after n2 steps is the straight-line continuation of the
+    state after n1 steps, folded by the two reflecting surfaces (Eq. 18, full reflection)."""
+    Lz = 100.0
+
+    def prob(n):
+        p = W.homogeneous(thickness=Lz, n_primaries=3000, n_steps=n, tau0=INF, tau_exp=0,
+                          dt=0.75, src_lambda=0.0)
+        return p
+
+    r1 = _run(oracle_lib, prob(3), records=True).records
+    r2 = _run(oracle_lib, prob(211), records=True).records
+    o1, o2 = np.argsort(r1["uid"]), np.argsort(r2["uid"])
+    z1, mu1 = r1["z"][o1], r1["mu"][o1]
+    z2, mu2 = r2["z"][o2], r2["mu"][o2]
+    assert np.array_equal(r1["uid"][o1], r2["uid"][o2])
+    v, t = W.V_AU, (211 - 3) * 0.75
+    # unfold state 1 so that the fold below reproduces it, then fly straight
+    u = z1 + v * mu1 * t
+    z_exp, sgn = _fold(u, Lz)
+    assert np.allclose(z2, z_exp, atol=1e-9, rtol=0)
+    assert np.array_equal(np.sign(mu2), np.sign(mu1) * sgn)
+    assert np.array_equal(np.abs(mu2), np.abs(mu1))
+    assert np.all(r2["ev"][:, 0] == 0)
+
+
+def _event_driven_flight(z, mu, layer, spin, tau, inst):
+    """Exact ballistic flight over time tau by hit times, T = 1 at every interface."""
+    zb = inst.z_bound
+    L = len(zb) - 1
+    for _ in range(10000):
+        v = inst.v[inst.ch_of[layer, spin]]
+        wall = zb[layer + 1] if mu > 0 else zb[layer]
+        t_hit = (wall - z) / (v * mu)
+        if t_hit >= tau:
+            return z + v * mu * tau, mu, layer
+        tau -= t_hit
+        z = wall
+        if mu > 0:
+            if layer == L - 1:
+                mu = -mu
+            else:
+                layer += 1
+        else:
+            if layer == 0:
+                mu = -mu
+            else:
+                layer -= 1
+    raise RuntimeError("too many hits")
+
+
+def test_ballistic_bilayer_transparent_event_driven(oracle_lib):
+    """tau -> infinity, T = 1 in a Fe/Au bilayer: the half-step transport with speed
+    rescaling at the interface equals an exact flight by interface hit times."""
+    def prob(n):
+        inst = W.make_instance(W.bilayer(15.0, 40.0), n_primaries=1500, n_steps=n,
+                               transparent=True, tau0=(INF, INF, INF, INF))
+        return W.Problem([inst], seed=3, dt=1.0, n_steps=n, state_fp64=True)
+
+    r1 = _run(oracle_lib, prob(2), records=True).records
+    r2 = _run(oracle_lib, prob(90), records=True).records
+    inst = prob(2).instances[0]
+    o1, o2 = np.argsort(r1["uid"]), np.argsort(r2["uid"])
+    for a, b in zip(o1, o2):
+        z, mu, l = _event_driven_flight(r1["z"][a], r1["mu"][a], r1["layer"][a],
+                                        r1["spin"][a], 88.0, inst)
+        assert abs(z - r2["z"][b]) < 1e-9
+        assert mu == r2["mu"][b]
+        assert l == r2["layer"][b]
+
+
+def test_interface_transmission_fraction(oracle_lib):
+    """Each interface hit is an independent Bernoulli(T) draw (Sec. III.A)."""
+    T = 0.3
+    inst = W.make_instance(W.bilayer(15.0, 20.0), n_primaries=4000, n_steps=400,
+                           T_values=(T, T, T, T), tau0=(INF, INF, INF, INF))
+    res = _run(oracle_lib, W.Problem([inst], seed=5, dt=1.0, n_steps=400, state_fp64=True))
+    names = oracle_lib.COUNTER_NAMES
+    tr = res.counters[:, names.index("transmit")].sum()
+    rf = res.counters[:, names.index("refl_if")].sum()
+    n = tr + rf
+    assert n > 5000
+    assert abs(tr / n - T) < 4 * math.sqrt(T * (1 - T) / n)
+
+
+# --------------------------------------------------------------------------- B: diffusion
+def _msd_discrete(n, p, v, h):
+    """Exact mean-square displacement of the split scheme after n steps of an infinite
+    medium with isotropic redraws at the mid-step points (probability p each)."""
+    q = 1.0 - p
+    a = np.arange(2 * n)
+    A, B = np.meshgrid(a, a, indexing="ij")
+    lo, hi = np.minimum(A, B), np.maximum(A, B)
+    k = np.maximum(0, (hi - 1) // 2 - (lo + 1) // 2 + 1)
+    k = np.where(lo == hi, 0, k)
+    return (v * h) ** 2 / 3.0 * np.sum(q ** k)
+
+
+def _alpha_eq21(t, tau):
+    e = 1.0 - math.exp(-t / tau)
+    return t * e / (t - tau * e)
+
+
+def test_mean_square_displacement_and_alpha(oracle_lib):
+    """Elastic scattering only, infinite medium (Fig. 2 setup: 1.5 eV, tau_el = 30 fs).
+    The sampled MSD matches the exact discrete-time MSD of the split scheme, and that
+    MSD's generalised diffusion exponent converges to the paper's Eq. (21)."""
+    dt, tau_el, v = 0.5, 30.0, W.V_AU
+    p = -math.expm1(-dt / tau_el)
+    msds = {}
+    for n in (20, 120, 400):
+        prob = W.homogeneous(thickness=2000.0, n_primaries=20000, n_steps=n, tau0=INF,
+                             tau_el=tau_el, tau_exp=0, dt=dt, src=(1000.0, 1000.0))
+        rec = _run(oracle_lib, prob, records=True).records
+        d2 = (rec["z"] - 1000.0) ** 2
+        exact = _msd_discrete(n, p, v, dt / 2)
+        se = d2.std() / math.sqrt(len(d2))
+        assert abs(d2.mean() - exact) < 4 * se, (n, d2.mean(), exact, se)
+        assert np.all(rec["ev"][:, 3] == 0) and np.all(rec["E"] == W.e_fx(1.5))
+        msds[n] = exact
+    # generalised diffusion exponent of the exact discrete MSD vs Eq. (21)
+    for n in (60, 200, 600):
+        s0, s1 = _msd_discrete(n, p, v, dt / 2), _msd_discrete(n + 2, p, v, dt / 2)
+        t = (n + 1) * dt
+        alpha = t * (s1 - s0) / (2 * dt) / (0.5 * (s0 + s1))
+        assert abs(alpha - _alpha_eq21(t, tau_el)) < 0.02, (n, alpha)
+    assert _alpha_eq21(1e-3, tau_el) == pytest.approx(2.0, abs=1e-3)
+    assert _alpha_eq21(1e5, tau_el) == pytest.approx(1.0, abs=1e-3)
+
+
+def test_short_tau_diffusion_mode_decay(oracle_lib):
+    """Short elastic time in a reflecting slab: the first Neumann cosine mode of the
+    density decays at D (pi/L)^2 with D the diffusion constant of the discrete scheme."""
+    Lz, dt, tau_el, v = 20.0, 0.25, 1.0, W.V_AU
+    p = -math.expm1(-dt / tau_el)
+    # D of the discrete walk from the exact MSD's linear growth
+    D = (_msd_discrete(402, p, v, dt / 2) - _msd_discrete(400, p, v, dt / 2)) / (2 * 2 * dt)
+    k = math.pi / Lz
+    amps = []
+    for n in (120, 360):
+        prob = W.homogeneous(thickness=Lz, n_primaries=40000, n_steps=n, tau0=INF,
+                             tau_el=tau_el, tau_exp=0, dt=dt, src=(4.0, 4.0))
+        rec = _run(oracle_lib, prob, records=True).records
+        c = np.cos(k * rec["z"])
+        amps.append((c.mean(), c.std() / math.sqrt(len(c))))
+    ratio = amps[1][0] / amps[0][0]
+    expect = math.exp(-D * k * k * (360 - 120) * dt)
+    err = ratio * math.hypot(amps[0][1] / amps[0][0], amps[1][1] / amps[1][0])
+    assert abs(ratio - expect) < 4 * err + 0.01, (ratio, expect, err)
+
+
+# --------------------------------------------------------------------------- C: cascade
+def _alive_expectation(n, p, x):
+    """E[N_alive] of one primary after n steps: each alive carrier splits with
+    probability p per step into two carriers whose energies are E times independent
+    uniforms; a carrier whose energy fraction falls below x is removed."""
+    tot = 0.0
+    for k in range(n + 1):
+        m_k = math.comb(n, k) * (2 * p) ** k * (1 - p) ** (n - k)
+        if k == 0 or x <= 0:
+            surv = 1.0
+        else:
+            lx = -math.log(x)
+            surv = 1.0 - x * sum(lx ** j / math.factorial(j) for j in range(k))
+        tot += m_k * surv
+    return tot
+
+
+@pytest.mark.parametrize("e_min", [0.0, 0.1])
+def test_cascade_closed_form(oracle_lib, e_min):
+    """Constant lifetime (Fig. 3 setting): mean number of hot carriers per primary."""
+    n, dt, tau = 40, 1.0, 30.0
+    p = -math.expm1(-dt / tau)
+    prob = W.homogeneous(thickness=60.0, n_primaries=8000, n_steps=n, tau0=tau, tau_exp=0,
+                         dt=dt, e_min_ev=e_min, e0_ev=1.5)
+    res = _run(oracle_lib, prob, records=True)
+    rec = res.records
+    alive = rec["dead"] < 0
+    per_root = np.bincount((rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64)[alive],
+                           minlength=8000)
+    exp = _alive_expectation(n, p, e_min / 1.5)
+    se = per_root.std() / math.sqrt(len(per_root))
+    assert abs(per_root.mean() - exp) < 4 * se, (per_root.mean(), exp, se)
+    assert res.counters[-1, 9] == alive.sum()
+
+
+def test_cascade_energy_histogram(oracle_lib):
+    """Energy spectrum of the cascade after n steps (E_min = 0): a carrier with k splits
+    has energy E0*prod(U_i), density (ln(E0/E))^(k-1)/((k-1)! E0)."""
+    n, dt, tau, E0 = 30, 1.0, 20.0, 1.6
+    p = -math.expm1(-dt / tau)
+    edges = W.energy_edges(0.1, 1.6)
+    prob = W.homogeneous(thickness=60.0, n_primaries=6000, n_steps=n, tau0=tau, tau_exp=0,
+                         dt=dt, e_min_ev=0.0, e0_ev=E0, e_edges=edges)
+    res = _run(oracle_lib, prob)
+    hist = res.dens[0][-1].sum(axis=(0, 2)).astype(float) / 6000
+    lo = np.arange(16) * 0.1
+    hi = lo + 0.1
+
+    def cdf_k(e, k):   # P(E0 prod U <= e) for k >= 1
+        x = e / E0
+        if x <= 0:
+            return 0.0
+        lx = -math.log(x)
+        return x * sum(lx ** j / math.factorial(j) for j in range(k))
+
+    expect = np.zeros(16)
+    for k in range(1, n + 1):
+        m_k = math.comb(n, k) * (2 * p) ** k * (1 - p) ** (n - k)
+        expect += m_k * np.array([cdf_k(b, k) - cdf_k(a, k) for a, b in zip(lo, hi)])
+    expect[-1] += (1 - p) ** n          # never-split primaries sit at E0 (last bin)
+    se = np.sqrt(np.maximum(expect, 1e-3) * 4 / 6000)   # generous Poisson-cluster error
+    assert np.all(np.abs(hist - expect) < 4 * se + 1e-3), np.c_[hist, expect]
+
+
+# --------------------------------------------------------------------------- D, E, F
+def test_conservation_counts_energy_and_bound(oracle_lib):
+    """Integer conservation every step (Eq. 17), exact energy conservation of the
+    e-e events (Sec. III.A) and the per-tree alive bound floor(E0/E_min)."""
+    prob = W.config0(n_primaries=3000, n_steps=150)
+    res = _run(oracle_lib, prob, records=True)
+    c = res.counters
+    names = oracle_lib.COUNTER_NAMES
+    col = {k: c[:, names.index(k)] for k in names}
+    net = np.cumsum(col["injected"] + col["spawned"] - col["absorbed"])
+    assert np.array_equal(net, col["alive"])
+    assert np.array_equal(res.dens[0].sum(axis=(1, 2, 3)).astype(np.int64), col["alive"])
+    rec = res.records
+    alive = rec["dead"] < 0
+    e_alive = int(rec["E"][alive].astype(np.int64).sum())
+    assert e_alive + int(col["e_absorbed"].sum()) == 3000 * W.e_fx(1.5)
+    roots = (rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    per_root = np.bincount(roots[alive], minlength=3000)
+    assert per_root.max() <= W.e_fx(1.5) // prob.e_min_fx
+    # spawns recorded per particle add up to the spawn counter
+    assert rec["ev"][:, 3].sum() == col["spawned"].sum()
+    assert len(rec["uid"]) == 3000 + col["spawned"].sum()
+
+
+def test_fp32_state_is_representable(oracle_lib):
+    prob = W.config1(n_primaries=500, n_steps=60)
+    rec = _run(oracle_lib, prob, records=True).records
+    assert np.array_equal(rec["z"].astype(np.float32).astype(np.float64), rec["z"])
+    assert np.array_equal(rec["mu"].astype(np.float32).astype(np.float64), rec["mu"])
+    zb = prob.instances[0].z_bound
+    assert np.all(rec["z"] >= zb[rec["layer"]]) and np.all(rec["z"] <= zb[rec["layer"] + 1])
+
+
+# --------------------------------------------------------------------------- G: T = 1
+def test_split_layer_invariance(oracle_lib):
+    """Splitting a homogeneous layer into two identical layers joined by T = 1 changes
+    nothing but the transmission count: the bins are bitwise identical."""
+    base = dict(thickness=50.0, n_primaries=2000, n_steps=120, tau0=25.0, tau_el=40.0,
+                e_min_ev=0.1, e_edges=W.energy_edges(0.25, 2.0), src=(0.0, 50.0))
+    a = _run(oracle_lib, W.homogeneous(**base), records=True)
+    b = _run(oracle_lib, W.homogeneous(split_at=21.0, **base), records=True)
+    assert np.array_equal(a.dens[0], b.dens[0])
+    assert np.array_equal(a.cur[0], b.cur[0])
+    names = oracle_lib.COUNTER_NAMES
+    keep = [i for i, k in enumerate(names) if k != "transmit"]
+    assert np.array_equal(a.counters[:, keep], b.counters[:, keep])
+    assert b.counters[:, names.index("transmit")].sum() > 100
+    oa, ob = np.argsort(a.records["uid"]), np.argsort(b.records["uid"])
+    assert np.array_equal(a.records["z"][oa], b.records["z"][ob])
+
+
+# --------------------------------------------------------------------------- H: event trees
+def test_event_tree_enumeration(oracle_lib):
+    """One primary, constant tau, E_min = 0, 6 steps: the distribution of the number of
+    carriers equals the exact enumeration of all split trees (chi^2)."""
+    from scipy import stats
+    n, dt, tau, N = 6, 1.0, 5.0, 30000
+    p = -math.expm1(-dt / tau)
+    dist = {1: 1.0}
+    for _ in range(n):
+        nxt = {}
+        for m, pm in dist.items():
+            for j in range(m + 1):
+                pr = pm * math.comb(m, j) * p ** j * (1 - p) ** (m - j)
+                nxt[m + j] = nxt.get(m + j, 0.0) + pr
+        dist = nxt
+    prob = W.homogeneous(thickness=40.0, n_primaries=N, n_steps=n, tau0=tau, tau_exp=0,
+                         dt=dt, e_min_ev=0.0)
+    rec = _run(oracle_lib, prob, records=True).records
+    per_root = np.bincount((rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64), minlength=N)
+    obs = np.bincount(per_root, minlength=65)[1:65].astype(float)
+    exp = np.array([dist.get(m, 0.0) for m in range(1, 65)]) * N
+    # merge the sparse tail
+    cut = np.where(exp < 5)[0]
+    first = cut[0] if len(cut) else len(exp)
+    o = np.append(obs[:first], obs[first:].sum())
+    e = np.append(exp[:first], exp[first:].sum())
+    chi2 = ((o - e) ** 2 / e).sum()
+    assert stats.chi2.sf(chi2, len(o) - 1) > 1e-3, (o, e)
+
+
+# --------------------------------------------------------------------------- source
+def test_injection_distributions(oracle_lib):
+    """Primaries: depth ~ exp(-z/15 nm) truncated to the Fe layer, cos(theta) uniform,
+    60 % spin up, energies uniform in [0.5, 2.0) eV (standard spin-valve pump)."""
+    prob = W.config1(n_primaries=40000, n_steps=1)
+    prob = replace(prob, instances=[replace(prob.instances[0],
+                                            v=np.zeros(4), inv_tau0=np.zeros(4))])
+    # frozen and collision-free: the records are the injected primaries
+    res = _run(oracle_lib, prob, records=True)
+    rec = {k: v[_primaries(res.records)] for k, v in res.records.items()}
+    z = rec["z"]
+    lam, d = 15.0, 15.0
+    mean_exp = lam - d * math.exp(-d / lam) / (1 - math.exp(-d / lam))
+    assert abs(z.mean() - mean_exp) < 4 * z.std() / math.sqrt(len(z))
+    assert z.max() <= 15.0 and z.min() >= 0.0
+    up = (rec["spin"] == 0).mean()
+    assert abs(up - 0.6) < 4 * math.sqrt(0.24 / len(z))
+    assert np.all(rec["ev"] == 0)
+    E = rec["E"] / W.E_ONE
+    assert E.min() >= 0.5 and E.max() < 2.0
+    assert abs(E.mean() - 1.25) < 4 * E.std() / math.sqrt(len(E))
+    mu = rec["mu"]
+    assert abs(mu.mean()) < 4 * mu.std() / math.sqrt(len(mu))
