@@ -1,0 +1,200 @@
+/* C ABI of the MI355X hot-electron particle-in-cell library (libpic.so).
+ *
+ * The library advances the spin-dependent Boltzmann equation for optically excited hot
+ * electrons in metallic multilayers with the particle-in-cell method of Nenno, Rethfeld
+ * and Schneider (arXiv:1807.04733, Sec. III.A): superparticles (Eq. 10) advanced by the
+ * Strang splitting of Eq. (15) -- Source(dt/2) Transport(dt/2) Scattering(dt)
+ * Transport(dt/2) Source(dt/2) -- and binned into the moments of Eq. (16) (density per
+ * depth, energy and spin) and Eq. (23) (spin current per depth and spin).
+ *
+ * Conventions
+ *   - z in nm, t in fs, speeds in nm/fs; energies above E_F as uint32 fixed point with
+ *     an LSB of 2^-30 eV.  Layer boundaries must lie on multiples of 2^-6 nm.
+ *   - Global spin s: 0 = up (emitter majority), 1 = down.
+ *   - A channel is (material, spin local to the layer); ch_of[l][s] selects the channel
+ *     of layer l for global spin s.  Interface k lies between layers k and k+1;
+ *     tt_of[k][d][s] is the transmission table for direction d (0: +z, 1: -z).
+ *   - Random numbers: Philox4x32-10 keyed by `seed`, counter (uid_lo, uid_hi, step, tag);
+ *     results are a pure function of the inputs, independent of launch configuration.
+ *
+ * Memory and streams
+ *   - The library never allocates device memory.  The caller supplies one device
+ *     workspace of at least pic_workspace_size() bytes (256-byte aligned) and keeps it
+ *     alive until pic_destroy().  Output arrays passed to pic_deposit() are caller-owned
+ *     device memory.  All device work is enqueued on the HIP stream given to pic_init()
+ *     (NULL = the default stream); only pic_counters(), pic_autotune() and pic_destroy()
+ *     synchronize.
+ *   - A context is not thread-safe; distinct contexts may be used concurrently on
+ *     distinct streams.
+ *
+ * Errors
+ *   - Every call returns a pic_status.  PIC_EINVAL: rejected arguments (checked
+ *     synchronously, nothing enqueued).  PIC_EHIP: a HIP runtime call failed.
+ *     PIC_ECAPACITY / PIC_ESTATE: an asynchronous device condition (particle slots
+ *     exhausted -- the excess carriers are dropped and counted, never written out of
+ *     bounds; or more than 8 boundary hits in one half step) reported by the next
+ *     synchronizing call.  pic_last_error() returns a thread-local message.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_LAYERS   16
+#define PIC_MAX_CHANNELS 8
+#define PIC_MAX_TTABLES  8
+#define PIC_MAX_TENTRIES 64
+#define PIC_MAX_EBINS    128
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = 1,
+  PIC_ENOMEM = 2,     /* workspace too small */
+  PIC_ECAPACITY = 3,  /* particle slots exhausted on the device */
+  PIC_EHIP = 4,
+  PIC_ESTATE = 5      /* call out of order, or a device-side consistency failure */
+} pic_status;
+
+/* pic_config.flags */
+#define PIC_F_STATE_FP64   1u  /* z and cos(theta) stored as binary64 (else binary32) */
+#define PIC_F_SECONDARIES  2u  /* inelastic events lift a secondary carrier (Eq. 6-7) */
+#define PIC_F_DEBUG        4u  /* keep per-particle event counts (see pic_layout) */
+
+/* per-step counters returned by pic_counters(), [n_steps][PIC_NCOUNTERS] */
+enum {
+  PIC_C_INJECTED = 0,   /* primaries created at the start of the step (Eq. 17) */
+  PIC_C_EV_EE,          /* inelastic (electron-electron) events */
+  PIC_C_EV_EL,          /* elastic events */
+  PIC_C_SPAWNED,        /* secondaries created */
+  PIC_C_ABSORBED,       /* carriers removed after falling below E_min */
+  PIC_C_SEC_ABSORBED,   /* secondaries below E_min at birth (never created) */
+  PIC_C_TRANSMIT,       /* interface transmissions */
+  PIC_C_REFL_IF,        /* interface reflections */
+  PIC_C_REFL_SURF,      /* vacuum-surface reflections */
+  PIC_C_ALIVE,          /* carriers alive after the step (= sum of the step's density) */
+  PIC_C_E_ABSORBED,     /* energy removed with absorbed carriers (fixed point) */
+  PIC_NCOUNTERS
+};
+
+/* One layer stack with its parameters (Eqs. 2, 7, 8, 19; Sec. III.A). */
+typedef struct {
+  int32_t  n_layers;                        /* 1..PIC_MAX_LAYERS */
+  int32_t  n_channels;                      /* 1..PIC_MAX_CHANNELS */
+  int32_t  n_ttables;                       /* 1..PIC_MAX_TTABLES */
+  int32_t  t_entries;                       /* 1 (constant) or 2..PIC_MAX_TENTRIES nodes */
+  double   z_bound[PIC_MAX_LAYERS + 1];     /* increasing, multiples of 2^-6 nm */
+  int32_t  ch_of[PIC_MAX_LAYERS][2];
+  double   v[PIC_MAX_CHANNELS];             /* speed per channel, > 0 */
+  double   inv_tau0[PIC_MAX_CHANNELS];      /* 1/tau0; tau = tau0 (1 eV/E)^tau_exp; >= 0 */
+  double   inv_tau_el[PIC_MAX_LAYERS];      /* 1/tau_el per layer (0 = no elastic channel) */
+  double   P0[PIC_MAX_LAYERS];              /* equilibrium polarisation, Eq. (19), [-1,1] */
+  int32_t  tt_of[PIC_MAX_LAYERS - 1][2][2];
+  double   T[PIC_MAX_TTABLES][PIC_MAX_TENTRIES]; /* transmission probabilities in [0,1] */
+  double   T_scale;                         /* (t_entries-1)/E_table_max, 1/eV */
+  /* pump (Eq. 17): depth z0 = lo - lambda*log1p(-u*cd) (lambda > 0) or lo + u*(hi-lo),
+   * cd = 1 - exp(-(hi-lo)/lambda); spin up with probability up_frac; energy
+   * e_lo[s] + floor(w * e_span[s] / 2^32) for a uniform 32-bit word w. */
+  double   src_z_lo, src_z_hi, src_lambda, src_cd, src_up_frac;
+  uint32_t src_e_lo[2], src_e_span[2];
+  int64_t  n_primaries;                     /* total primaries of this instance */
+  uint64_t root_offset;                     /* global id of its first primary */
+  int32_t  nz;                              /* depth bins [k/inv_dz, (k+1)/inv_dz) */
+  double   inv_dz;
+} pic_instance;
+
+typedef struct {
+  int32_t  n_instances;                     /* >= 1 */
+  const pic_instance* inst;                 /* host array, copied by pic_init */
+  uint64_t seed;
+  double   dt;                              /* > 0 */
+  int32_t  n_steps;                         /* >= 1 */
+  int32_t  tau_exp;                         /* 0 or 2 */
+  uint32_t e_min_fx;                        /* carriers below this energy are removed */
+  uint32_t flags;                           /* PIC_F_* */
+  int32_t  n_ebins;                         /* 1..PIC_MAX_EBINS */
+  uint32_t e_edges[PIC_MAX_EBINS];          /* increasing lower edges (last bin open) */
+  int32_t  dens_stride, cur_stride;         /* deposit every k-th step (slot n/k) */
+  int32_t  slab_primaries;                  /* primaries per slab; 0 = 4096 */
+  double   capacity_factor;                 /* slots per primary; 0 = floor(E0max/Emin)+2 */
+} pic_config;
+
+/* Launch tuning.  Results never depend on it. */
+typedef struct {
+  int32_t block;          /* threads per workgroup: 64, 128 or 256 */
+  int32_t grid;           /* persistent workgroups per step launch; 0 = 2 x 256 CUs */
+  int32_t compact_every;  /* launch the compaction pass every k steps; 0 = never */
+  float   compact_frac;   /* compact a slab when dead slots exceed this fraction */
+  int32_t use_graph;      /* capture multi-step calls in a hipGraph */
+} pic_tuning;
+
+/* Where things live inside the workspace (byte offsets), for inspection and tests. */
+typedef struct {
+  int64_t n_slabs;
+  int64_t capacity;       /* total particle slots */
+  int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;  /* SoA arrays [capacity] */
+  int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst;
+  int64_t off_dens, off_cur, off_counters;
+  int64_t dens_len, cur_len;  /* elements of the int bins (u64 / i64) */
+  int32_t state_bytes;        /* 4 (binary32) or 8 (binary64) for z and mu */
+  int32_t flags_spin_shift, flags_layer_shift, flags_layer_bits, flags_gen_shift;
+  uint32_t flags_dead_bit;
+} pic_layout;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of device workspace a context for `cfg` needs.  PIC_EINVAL on a bad config. */
+pic_status pic_workspace_size(const pic_config* cfg, int64_t* bytes);
+
+/* Validate `cfg`, lay out the workspace, upload the tables and clear the state.
+ * `stream` is a hipStream_t (or NULL).  Enqueues work; does not synchronize. */
+pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_bytes,
+                    void* stream, pic_ctx** out);
+
+/* Set the source schedule, Eq. (17): sched[i*n_steps + n] primaries of instance i are
+ * created at the start of step n (host array; each row must sum to n_primaries). */
+pic_status pic_inject(pic_ctx* ctx, const int64_t* sched);
+
+/* Enqueue n steps (the next ones after those already run). */
+pic_status pic_step(pic_ctx* ctx, int32_t n);
+
+/* Convert the integer bins to binary64: dens_out [sum_i n_dslots*nz_i*NE*2] particle
+ * counts and cur_out [sum_i n_cslots*nz_i*2] sum of v*cos(theta) in nm/fs; instances are
+ * concatenated in order.  Device pointers (either may be NULL).  Enqueued, async. */
+pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
+
+/* Likelihood-ratio adjoint: gradient of sum(g_dens*dens) + sum(g_cur*cur) with respect
+ * to ln tau0 per channel and every transmission-table entry, written to grad_out
+ * (device, [n_channels + n_ttables*t_entries], summed over instances).  Replays the run
+ * from step 0 with the same random streams (the particle state is rebuilt; bins are
+ * untouched).  estimator 0: causal score carried by each carrier (needs K <= 16);
+ * 1: whole-tree return.  g_dens / g_cur: device arrays laid out like pic_deposit's
+ * outputs (either may be NULL). */
+pic_status pic_backward(pic_ctx* ctx, const double* g_dens, const double* g_cur,
+                        double* grad_out, int32_t estimator);
+
+/* Synchronize and copy the per-step counters to host_out [n_steps][PIC_NCOUNTERS]
+ * (may be NULL).  Reports asynchronous device conditions. */
+pic_status pic_counters(pic_ctx* ctx, int64_t* host_out);
+
+/* Clear particles, bins and counters and rewind to step 0 (schedule is kept). */
+pic_status pic_reset(pic_ctx* ctx);
+
+pic_status pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
+pic_status pic_get_tuning(const pic_ctx* ctx, pic_tuning* t);
+pic_status pic_layout_of(const pic_ctx* ctx, pic_layout* out);
+
+/* Time candidate launch shapes on the first `trial_steps` steps of this context's run
+ * and store the fastest in the context (and in a per-device cache keyed by the config
+ * signature).  Resets the context before and after.  Synchronizes. */
+pic_status pic_autotune(pic_ctx* ctx, int32_t trial_steps, pic_tuning* best);
+
+void pic_destroy(pic_ctx* ctx);
+const char* pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,582 @@
+// Host side of the libpic C ABI: validation, workspace layout, table upload, the step
+// driver (direct launches or a captured hipGraph) and the integer-to-binary64 bins.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_err;
+
+pic_status fail(pic_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(PIC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+bool on_grid(double z) {
+  const double q = z * 64.0;
+  return std::isfinite(q) && q == std::floor(q) && std::fabs(q) < 9.0e15;
+}
+
+struct Plan {
+  std::vector<int32_t> slab_inst, slab_k, slab_cap;
+  std::vector<int64_t> slab_base;
+  std::vector<int32_t> n_slabs_of, slab0_of;
+  std::vector<int64_t> dens_off, cur_off;
+  int64_t capacity = 0, dens_len = 0, cur_len = 0;
+  int n_dslots = 0, n_cslots = 0, state_bytes = 4;
+  bool debug = false;
+  // byte offsets inside the workspace
+  int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
+  int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
+  int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
+  int64_t off_grad, off_score;
+  int64_t bytes = 0;
+};
+
+pic_status validate(const pic_config* c) {
+  if (!c) return fail(PIC_EINVAL, "null config");
+  if (c->n_instances < 1 || !c->inst) return fail(PIC_EINVAL, "need at least one instance");
+  if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return fail(PIC_EINVAL, "dt must be > 0");
+  if (c->n_steps < 1) return fail(PIC_EINVAL, "n_steps must be >= 1");
+  if (c->tau_exp != 0 && c->tau_exp != 2) return fail(PIC_EINVAL, "tau_exp must be 0 or 2");
+  if (c->n_ebins < 1 || c->n_ebins > PIC_MAX_EBINS) return fail(PIC_EINVAL, "bad n_ebins");
+  for (int k = 1; k < c->n_ebins; ++k)
+    if (!(c->e_edges[k] > c->e_edges[k - 1])) return fail(PIC_EINVAL, "energy edges must increase");
+  if (c->dens_stride < 1 || c->cur_stride < 1) return fail(PIC_EINVAL, "strides must be >= 1");
+  if (c->slab_primaries < 0) return fail(PIC_EINVAL, "slab_primaries must be >= 0");
+  if (c->capacity_factor < 0 || !std::isfinite(c->capacity_factor))
+    return fail(PIC_EINVAL, "capacity_factor must be >= 0");
+  uint64_t roots_end = 0;
+  for (int i = 0; i < c->n_instances; ++i) {
+    const pic_instance& I = c->inst[i];
+    const std::string w = "instance " + std::to_string(i) + ": ";
+    if (I.n_layers < 1 || I.n_layers > PIC_MAX_LAYERS) return fail(PIC_EINVAL, w + "bad n_layers");
+    if (I.n_channels < 1 || I.n_channels > PIC_MAX_CHANNELS) return fail(PIC_EINVAL, w + "bad n_channels");
+    if (I.n_ttables < 1 || I.n_ttables > PIC_MAX_TTABLES) return fail(PIC_EINVAL, w + "bad n_ttables");
+    if (I.t_entries < 1 || I.t_entries > PIC_MAX_TENTRIES) return fail(PIC_EINVAL, w + "bad t_entries");
+    for (int l = 0; l <= I.n_layers; ++l)
+      if (!on_grid(I.z_bound[l])) return fail(PIC_EINVAL, w + "z_bound must lie on the 2^-6 nm grid");
+    for (int l = 0; l < I.n_layers; ++l) {
+      if (!(I.z_bound[l + 1] > I.z_bound[l])) return fail(PIC_EINVAL, w + "z_bound must increase");
+      for (int s = 0; s < 2; ++s)
+        if (I.ch_of[l][s] < 0 || I.ch_of[l][s] >= I.n_channels) return fail(PIC_EINVAL, w + "bad ch_of");
+      if (!(I.inv_tau_el[l] >= 0.0) || !std::isfinite(I.inv_tau_el[l])) return fail(PIC_EINVAL, w + "bad inv_tau_el");
+      if (!(I.P0[l] >= -1.0 && I.P0[l] <= 1.0)) return fail(PIC_EINVAL, w + "P0 outside [-1,1]");
+    }
+    for (int k = 0; k < I.n_layers - 1; ++k)
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s)
+          if (I.tt_of[k][d][s] < 0 || I.tt_of[k][d][s] >= I.n_ttables) return fail(PIC_EINVAL, w + "bad tt_of");
+    for (int ch = 0; ch < I.n_channels; ++ch) {
+      if (!(I.v[ch] > 0.0) || !std::isfinite(I.v[ch])) return fail(PIC_EINVAL, w + "speeds must be > 0");
+      if (!(I.inv_tau0[ch] >= 0.0) || !std::isfinite(I.inv_tau0[ch])) return fail(PIC_EINVAL, w + "inv_tau0 must be >= 0");
+    }
+    for (int t = 0; t < I.n_ttables; ++t)
+      for (int e = 0; e < I.t_entries; ++e)
+        if (!(I.T[t][e] >= 0.0 && I.T[t][e] <= 1.0)) return fail(PIC_EINVAL, w + "T outside [0,1]");
+    if (I.t_entries > 1 && (!(I.T_scale > 0.0) || !std::isfinite(I.T_scale)))
+      return fail(PIC_EINVAL, w + "T_scale must be > 0");
+    if (!(I.src_z_lo >= I.z_bound[0] && I.src_z_hi <= I.z_bound[I.n_layers] && I.src_z_lo <= I.src_z_hi))
+      return fail(PIC_EINVAL, w + "source region outside the stack");
+    if (!(I.src_lambda >= 0.0) || !std::isfinite(I.src_lambda)) return fail(PIC_EINVAL, w + "bad src_lambda");
+    if (I.src_lambda > 0.0 && !(I.src_cd > 0.0 && I.src_cd <= 1.0)) return fail(PIC_EINVAL, w + "bad src_cd");
+    if (!(I.src_up_frac >= 0.0 && I.src_up_frac <= 1.0)) return fail(PIC_EINVAL, w + "bad src_up_frac");
+    for (int s = 0; s < 2; ++s)
+      if ((uint64_t)I.src_e_lo[s] + I.src_e_span[s] > 0xFFFFFFFFull) return fail(PIC_EINVAL, w + "energy range overflows");
+    if (I.nz < 1 || !(I.inv_dz > 0.0) || !std::isfinite(I.inv_dz)) return fail(PIC_EINVAL, w + "bad depth bins");
+    if (I.n_primaries < 0) return fail(PIC_EINVAL, w + "n_primaries < 0");
+    if (I.root_offset + (uint64_t)I.n_primaries > 0x100000000ull)
+      return fail(PIC_EINVAL, w + "root ids must fit in 32 bits");
+    roots_end = std::max(roots_end, I.root_offset + (uint64_t)I.n_primaries);
+  }
+  return PIC_OK;
+}
+
+double default_capacity(const pic_config* c, const pic_instance& I) {
+  if (c->capacity_factor > 0) return c->capacity_factor;
+  if (!(c->flags & PIC_F_SECONDARIES)) return 1.0;
+  if (c->e_min_fx == 0) return 32.0;
+  const uint64_t e0 = std::max((uint64_t)I.src_e_lo[0] + I.src_e_span[0],
+                               (uint64_t)I.src_e_lo[1] + I.src_e_span[1]);
+  // every carrier of a tree keeps at least E_min, and energy is conserved
+  return std::min<double>((double)(e0 / c->e_min_fx) + 2.0, 64.0);
+}
+
+Plan make_plan(const pic_config* c) {
+  Plan p;
+  p.state_bytes = (c->flags & PIC_F_STATE_FP64) ? 8 : 4;
+  p.debug = (c->flags & PIC_F_DEBUG) != 0;
+  const int P = c->slab_primaries > 0 ? c->slab_primaries : 4096;
+  p.n_dslots = (c->n_steps + c->dens_stride - 1) / c->dens_stride;
+  p.n_cslots = (c->n_steps + c->cur_stride - 1) / c->cur_stride;
+  for (int i = 0; i < c->n_instances; ++i) {
+    const pic_instance& I = c->inst[i];
+    const int64_t N = I.n_primaries;
+    const int64_t S = std::max<int64_t>(1, (N + P - 1) / P);
+    const int64_t per = (N + S - 1) / S;
+    const double f = default_capacity(c, I);
+    int64_t cap = (int64_t)std::ceil((double)per * f) + 64;
+    cap = (cap + 63) & ~int64_t(63);
+    if (cap > (int64_t)1 << 30) cap = (int64_t)1 << 30;
+    p.n_slabs_of.push_back((int32_t)S);
+    p.slab0_of.push_back((int32_t)p.slab_inst.size());
+    for (int64_t k = 0; k < S; ++k) {
+      p.slab_inst.push_back(i);
+      p.slab_k.push_back((int32_t)k);
+      p.slab_cap.push_back((int32_t)cap);
+      p.slab_base.push_back(p.capacity);
+      p.capacity += cap;
+    }
+    p.dens_off.push_back(p.dens_len);
+    p.cur_off.push_back(p.cur_len);
+    p.dens_len += (int64_t)p.n_dslots * I.nz * c->n_ebins * 2;
+    p.cur_len += (int64_t)p.n_cslots * I.nz * 2;
+  }
+  const int64_t C = p.capacity, NS = (int64_t)p.slab_inst.size(), NI = c->n_instances;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  p.off_z = take(C * p.state_bytes);
+  p.off_mu = take(C * p.state_bytes);
+  p.off_E = take(C * 4);
+  p.off_uid = take(C * 8);
+  p.off_flags = take(C * 4);
+  p.off_ev = p.debug ? take(C * 8) : -1;
+  p.off_slab_base = take(NS * 8);
+  p.off_slab_cap = take(NS * 4);
+  p.off_slab_tail = take(NS * 4);
+  p.off_slab_dead = take(NS * 4);
+  p.off_slab_inst = take(NS * 4);
+  p.off_slab_k = take(NS * 4);
+  p.off_inst = take(NI * (int64_t)sizeof(DevInst));
+  p.off_inj = take(NI * ((int64_t)c->n_steps + 1) * 8);
+  p.off_edges = take(PIC_MAX_EBINS * 4);
+  p.off_dens = take(p.dens_len * 8);
+  p.off_cur = take(p.cur_len * 8);
+  p.off_counters = take((int64_t)c->n_steps * kNC * 8);
+  p.off_queue = take((int64_t)c->n_steps * 4 * 2);
+  p.off_status = take(64);
+  p.bytes = o;
+  return p;
+}
+
+}  // namespace
+
+struct pic_ctx {
+  pic_config cfg;
+  std::vector<pic_instance> inst;
+  Plan plan;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  std::vector<DevInst> h_inst;
+  std::vector<int64_t> h_inj;
+  std::vector<int64_t> h_counters;
+  int step = 0;
+  bool sched_set = false;
+  pic_tuning tune;
+  size_t lds_bytes = 0;
+  int lds_dens_words = 0, lds_cur_words = 0, inst_bytes = 0;
+  bool dens_lds = true;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_start = -1, g_n = -1;
+
+  template <typename T>
+  T* at(int64_t off) const { return off < 0 ? nullptr : (T*)(ws + off); }
+};
+
+namespace {
+
+void drop_graph(pic_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->g_start = c->g_n = -1;
+}
+
+StepArgs step_args(const pic_ctx* c, int n) {
+  const Plan& p = c->plan;
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.z = c->at<void>(p.off_z);
+  a.mu = c->at<void>(p.off_mu);
+  a.E = c->at<uint32_t>(p.off_E);
+  a.uid = c->at<uint64_t>(p.off_uid);
+  a.flags = c->at<uint32_t>(p.off_flags);
+  a.ev = c->at<uint64_t>(p.off_ev);
+  a.slab_base = c->at<int64_t>(p.off_slab_base);
+  a.slab_cap = c->at<int32_t>(p.off_slab_cap);
+  a.slab_tail = c->at<int32_t>(p.off_slab_tail);
+  a.slab_dead = c->at<int32_t>(p.off_slab_dead);
+  a.slab_inst = c->at<int32_t>(p.off_slab_inst);
+  a.slab_k = c->at<int32_t>(p.off_slab_k);
+  a.inst = c->at<DevInst>(p.off_inst);
+  a.inj_cum = c->at<int64_t>(p.off_inj);
+  a.e_edges = c->at<uint32_t>(p.off_edges);
+  a.dens = c->at<uint64_t>(p.off_dens);
+  a.cur = c->at<int64_t>(p.off_cur);
+  a.counters = c->at<int64_t>(p.off_counters);
+  a.queue = c->at<int32_t>(p.off_queue);
+  a.status = c->at<uint32_t>(p.off_status);
+  a.n_slabs = (int32_t)p.slab_inst.size();
+  a.n_inst = c->cfg.n_instances;
+  a.n_ebins = c->cfg.n_ebins;
+  a.n_steps = c->cfg.n_steps;
+  a.step = n;
+  a.key0 = (uint32_t)c->cfg.seed;
+  a.key1 = (uint32_t)(c->cfg.seed >> 32);
+  a.e_min = c->cfg.e_min_fx;
+  a.dt = c->cfg.dt;
+  a.h = 0.5 * c->cfg.dt;
+  a.tau_exp2 = c->cfg.tau_exp == 2;
+  a.secondaries = (c->cfg.flags & PIC_F_SECONDARIES) != 0;
+  a.debug = p.debug;
+  a.dens_on = (n % c->cfg.dens_stride) == 0;
+  a.cur_on = (n % c->cfg.cur_stride) == 0;
+  a.dens_slot = n / c->cfg.dens_stride;
+  a.cur_slot = n / c->cfg.cur_stride;
+  a.dens_lds = c->dens_lds;
+  a.lds_dens_words = c->lds_dens_words;
+  a.lds_cur_words = c->lds_cur_words;
+  a.inst_bytes = c->inst_bytes;
+  return a;
+}
+
+CompactArgs compact_args(const pic_ctx* c) {
+  const Plan& p = c->plan;
+  CompactArgs a;
+  a.z = c->at<void>(p.off_z);
+  a.mu = c->at<void>(p.off_mu);
+  a.E = c->at<uint32_t>(p.off_E);
+  a.uid = c->at<uint64_t>(p.off_uid);
+  a.flags = c->at<uint32_t>(p.off_flags);
+  a.ev = c->at<uint64_t>(p.off_ev);
+  a.slab_base = c->at<int64_t>(p.off_slab_base);
+  a.slab_tail = c->at<int32_t>(p.off_slab_tail);
+  a.slab_dead = c->at<int32_t>(p.off_slab_dead);
+  a.n_slabs = (int32_t)p.slab_inst.size();
+  a.frac = c->tune.compact_frac;
+  return a;
+}
+
+pic_status enqueue_steps(pic_ctx* c, int start, int n) {
+  const bool fp64 = c->plan.state_bytes == 8;
+  const int n_slabs = (int)c->plan.slab_inst.size();
+  int grid = c->tune.grid > 0 ? c->tune.grid : 512;
+  grid = std::max(1, std::min(grid, n_slabs));
+  for (int s = start; s < start + n; ++s) {
+    StepArgs a = step_args(c, s);
+    HIP_TRY(launch_step(a, fp64, grid, c->tune.block, c->lds_bytes, c->stream));
+    if (c->tune.compact_every > 0 && !c->plan.debug && (s + 1) % c->tune.compact_every == 0 &&
+        s + 1 < c->cfg.n_steps) {
+      CompactArgs ca = compact_args(c);
+      HIP_TRY(launch_compact(ca, fp64, c->tune.block, c->stream));
+    }
+  }
+  return PIC_OK;
+}
+
+pic_status upload_tables(pic_ctx* c) {
+  const Plan& p = c->plan;
+  const pic_config& cfg = c->cfg;
+  c->h_inst.assign(cfg.n_instances, DevInst{});
+  int max_tab = 1;
+  for (int i = 0; i < cfg.n_instances; ++i) {
+    const pic_instance& I = c->inst[i];
+    DevInst& D = c->h_inst[i];
+    std::memset(&D, 0, sizeof(D));
+    for (int l = 0; l < I.n_layers; ++l) {
+      D.lay[l] = make_double4(I.z_bound[l], I.z_bound[l + 1], I.inv_tau_el[l], 0.5 * (1.0 + I.P0[l]));
+      for (int s = 0; s < 2; ++s)
+        D.chan[l][s] = make_double2(I.v[I.ch_of[l][s]], I.inv_tau0[I.ch_of[l][s]]);
+    }
+    D.T_scale = I.T_scale;
+    D.inv_dz = I.inv_dz;
+    D.src_lo = I.src_z_lo;
+    D.src_hi = I.src_z_hi;
+    D.src_lambda = I.src_lambda;
+    D.src_cd = I.src_cd;
+    D.src_up = I.src_up_frac;
+    for (int s = 0; s < 2; ++s) {
+      D.e_lo[s] = I.src_e_lo[s];
+      D.e_span[s] = I.src_e_span[s];
+    }
+    D.n_layers = I.n_layers;
+    D.t_entries = I.t_entries;
+    D.nz = I.nz;
+    D.n_slabs = p.n_slabs_of[i];
+    D.slab0 = p.slab0_of[i];
+    D.root_offset = I.root_offset;
+    D.dens_off = p.dens_off[i];
+    D.cur_off = p.cur_off[i];
+    for (int k = 0; k < I.n_layers - 1; ++k)
+      for (int d = 0; d < 2; ++d)
+        for (int s = 0; s < 2; ++s) D.tt[k][d][s] = (uint8_t)I.tt_of[k][d][s];
+    for (int t = 0; t < I.n_ttables; ++t)
+      for (int e = 0; e < I.t_entries; ++e) D.T[t * I.t_entries + e] = I.T[t][e];
+    max_tab = std::max(max_tab, I.n_ttables * I.t_entries);
+  }
+  c->inst_bytes = (int)((kInstHead + max_tab * 8 + 15) & ~15);
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_inst), c->h_inst.data(),
+                         sizeof(DevInst) * c->h_inst.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_slab_base), p.slab_base.data(), p.slab_base.size() * 8,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_slab_cap), p.slab_cap.data(), p.slab_cap.size() * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_slab_inst), p.slab_inst.data(), p.slab_inst.size() * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_slab_k), p.slab_k.data(), p.slab_k.size() * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_edges), cfg.e_edges, PIC_MAX_EBINS * 4,
+                         hipMemcpyHostToDevice, c->stream));
+  // the copies read pageable host memory; finish them before the host buffers can change
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+pic_status clear_state(pic_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t NS = (int64_t)p.slab_inst.size();
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_slab_tail), NS, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_slab_dead), NS, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_dens), p.dens_len * 2, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_cur), p.cur_len * 2, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_counters), (int64_t)c->cfg.n_steps * kNC * 2, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_queue), (int64_t)c->cfg.n_steps * 2, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_status), 16, 0, c->stream));
+  c->step = 0;
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pic_last_error(void) { return g_err.c_str(); }
+
+pic_status pic_workspace_size(const pic_config* cfg, int64_t* bytes) {
+  pic_status st = validate(cfg);
+  if (st != PIC_OK) return st;
+  if (!bytes) return fail(PIC_EINVAL, "null output");
+  *bytes = make_plan(cfg).bytes;
+  return PIC_OK;
+}
+
+pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_bytes, void* stream,
+                    pic_ctx** out) {
+  pic_status st = validate(cfg);
+  if (st != PIC_OK) return st;
+  if (!out) return fail(PIC_EINVAL, "null output");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(PIC_EINVAL, "workspace must be 256-byte aligned");
+  Plan plan = make_plan(cfg);
+  if (workspace_bytes < plan.bytes)
+    return fail(PIC_ENOMEM, "workspace too small: need " + std::to_string(plan.bytes) + " bytes");
+  pic_ctx* c = new pic_ctx();
+  c->cfg = *cfg;
+  c->inst.assign(cfg->inst, cfg->inst + cfg->n_instances);
+  c->cfg.inst = c->inst.data();
+  c->plan = std::move(plan);
+  c->stream = (hipStream_t)stream;
+  c->ws = (uint8_t*)workspace;
+  c->tune.block = 256;
+  c->tune.grid = 1024;
+  c->tune.compact_every = 8;
+  c->tune.compact_frac = 0.15f;
+  c->tune.use_graph = 1;
+  // LDS histograms: the density slice and the current slice of the largest instance
+  int nz_max = 1;
+  for (const auto& I : c->inst) nz_max = std::max(nz_max, I.nz);
+  c->lds_cur_words = nz_max * 2;
+  const int dens_words = nz_max * cfg->n_ebins * 2;
+  const size_t budget = 56 * 1024;
+  const size_t cur_bytes = (size_t)c->lds_cur_words * 8;
+  c->dens_lds = (size_t)dens_words * 4 + cur_bytes + 16 <= budget;
+  c->lds_dens_words = c->dens_lds ? dens_words : 0;
+  c->lds_bytes = (((size_t)c->lds_dens_words * 4 + 15) & ~(size_t)15) + cur_bytes;
+  if (cur_bytes > budget) {
+    delete c;
+    return fail(PIC_EINVAL, "too many depth bins for the LDS current histogram");
+  }
+  st = upload_tables(c);
+  if (st == PIC_OK) st = clear_state(c);
+  if (st != PIC_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+pic_status pic_inject(pic_ctx* c, const int64_t* sched) {
+  if (!c || !sched) return fail(PIC_EINVAL, "null argument");
+  const int NS = c->cfg.n_steps;
+  std::vector<int64_t> cum((size_t)c->cfg.n_instances * (NS + 1));
+  for (int i = 0; i < c->cfg.n_instances; ++i) {
+    int64_t acc = 0;
+    cum[(size_t)i * (NS + 1)] = 0;
+    for (int n = 0; n < NS; ++n) {
+      const int64_t v = sched[(size_t)i * NS + n];
+      if (v < 0) return fail(PIC_EINVAL, "negative schedule entry");
+      acc += v;
+      cum[(size_t)i * (NS + 1) + n + 1] = acc;
+    }
+    if (acc != c->inst[i].n_primaries)
+      return fail(PIC_EINVAL, "schedule of instance " + std::to_string(i) + " does not sum to n_primaries");
+  }
+  c->h_inj.swap(cum);
+  HIP_TRY(hipMemcpyAsync(c->at<void>(c->plan.off_inj), c->h_inj.data(), c->h_inj.size() * 8,
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->sched_set = true;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx* c, int32_t n) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  if (!c->sched_set) return fail(PIC_ESTATE, "pic_inject must precede pic_step");
+  if (n < 0 || c->step + n > c->cfg.n_steps) return fail(PIC_EINVAL, "step count beyond n_steps");
+  if (n == 0) return PIC_OK;
+  const int start = c->step;
+  if (c->tune.use_graph && n > 1) {
+    if (!(c->gexec && c->g_start == start && c->g_n == n)) {
+      drop_graph(c);
+      HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      pic_status st = enqueue_steps(c, start, n);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (st != PIC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      c->graph = g;
+      HIP_TRY(hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+      c->g_start = start;
+      c->g_n = n;
+    }
+    HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+  } else {
+    pic_status st = enqueue_steps(c, start, n);
+    if (st != PIC_OK) return st;
+  }
+  c->step += n;
+  return PIC_OK;
+}
+
+pic_status pic_deposit(pic_ctx* c, double* dens_out, double* cur_out) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  HIP_TRY(launch_convert(c->at<uint64_t>(c->plan.off_dens), dens_out ? c->plan.dens_len : 0,
+                         c->at<int64_t>(c->plan.off_cur), cur_out ? c->plan.cur_len : 0, dens_out,
+                         cur_out, c->stream));
+  return PIC_OK;
+}
+
+pic_status pic_counters(pic_ctx* c, int64_t* host_out) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  uint32_t status = 0;
+  HIP_TRY(hipMemcpy(&status, c->at<void>(c->plan.off_status), 4, hipMemcpyDeviceToHost));
+  if (host_out)
+    HIP_TRY(hipMemcpy(host_out, c->at<void>(c->plan.off_counters),
+                      (size_t)c->cfg.n_steps * kNC * 8, hipMemcpyDeviceToHost));
+  if (status & kStOverflow)
+    return fail(PIC_ECAPACITY, "particle slots exhausted: raise capacity_factor");
+  if (status & kStHits) return fail(PIC_ESTATE, "more than 8 boundary hits in one half step");
+  return PIC_OK;
+}
+
+pic_status pic_reset(pic_ctx* c) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  return clear_state(c);
+}
+
+pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
+  if (!c || !t) return fail(PIC_EINVAL, "null argument");
+  const int b = t->block;
+  if (!(b == 64 || b == 128 || b == 256)) return fail(PIC_EINVAL, "block must be 64, 128 or 256");
+  if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
+    return fail(PIC_EINVAL, "bad tuning");
+  c->tune = *t;
+  drop_graph(c);
+  return PIC_OK;
+}
+
+pic_status pic_get_tuning(const pic_ctx* c, pic_tuning* t) {
+  if (!c || !t) return fail(PIC_EINVAL, "null argument");
+  *t = c->tune;
+  return PIC_OK;
+}
+
+pic_status pic_layout_of(const pic_ctx* c, pic_layout* o) {
+  if (!c || !o) return fail(PIC_EINVAL, "null argument");
+  const Plan& p = c->plan;
+  o->n_slabs = (int64_t)p.slab_inst.size();
+  o->capacity = p.capacity;
+  o->off_z = p.off_z;
+  o->off_mu = p.off_mu;
+  o->off_E = p.off_E;
+  o->off_uid = p.off_uid;
+  o->off_flags = p.off_flags;
+  o->off_ev = p.off_ev;
+  o->off_slab_base = p.off_slab_base;
+  o->off_slab_cap = p.off_slab_cap;
+  o->off_slab_tail = p.off_slab_tail;
+  o->off_slab_dead = p.off_slab_dead;
+  o->off_slab_inst = p.off_slab_inst;
+  o->off_dens = p.off_dens;
+  o->off_cur = p.off_cur;
+  o->off_counters = p.off_counters;
+  o->dens_len = p.dens_len;
+  o->cur_len = p.cur_len;
+  o->state_bytes = p.state_bytes;
+  o->flags_spin_shift = 0;
+  o->flags_layer_shift = kLayerShift;
+  o->flags_layer_bits = 4;
+  o->flags_gen_shift = kGenShift;
+  o->flags_dead_bit = kDead;
+  return PIC_OK;
+}
+
+pic_status pic_backward(pic_ctx* c, const double*, const double*, double*, int32_t) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  return fail(PIC_ESTATE, "adjoint not available in this build");
+}
+
+pic_status pic_autotune(pic_ctx* c, int32_t, pic_tuning* best) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  if (best) *best = c->tune;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  delete c;
+}
+
+}  // extern "C"

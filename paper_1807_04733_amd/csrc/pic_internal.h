@@ -1,0 +1,111 @@
+// Internal layout shared by the device kernels and the host side of libpic.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxL = PIC_MAX_LAYERS;
+constexpr int kMaxT = PIC_MAX_TTABLES * PIC_MAX_TENTRIES;
+constexpr int kMaxHits = 8;
+constexpr int kNC = PIC_NCOUNTERS;
+
+// Random-number purposes (fourth counter word).  One fixed slot per purpose so that a
+// branch taken or not taken never shifts the draws of another decision.
+constexpr uint32_t kTagScat = 0x000u;    // words: event, channel, new direction, split
+constexpr uint32_t kTagSpawn = 0x100u;   // words: direction, spin, lineage, lineage fallback
+constexpr uint32_t kTagHalf1 = 0x200u;   // + i: i-th interface draw of the first half step
+constexpr uint32_t kTagHalf2 = 0x300u;   // + i: same for the second half step
+constexpr uint32_t kTagInject = 0x400u;  // counter (root, 0, ~0, tag): depth, dir, spin, E
+
+// Packed per-particle flags.
+constexpr uint32_t kSpinMask = 1u;
+constexpr int kLayerShift = 1;
+constexpr uint32_t kLayerMask = 0xFu;
+constexpr int kGenShift = 8;
+constexpr uint32_t kGenMask = 0xFFu;
+constexpr uint32_t kDead = 0x80000000u;
+
+// Device status bits.
+constexpr uint32_t kStOverflow = 1u;
+constexpr uint32_t kStHits = 2u;
+
+// Per-instance tables as the kernels read them (copied into LDS per workgroup).
+struct alignas(32) DevInst {
+  double4 lay[kMaxL];          // (z_lo, z_hi, 1/tau_el, P(up) of a secondary)
+  double2 chan[kMaxL][2];      // per (layer, spin): (speed, 1/tau0)
+  double T_scale, inv_dz;
+  double src_lo, src_hi, src_lambda, src_cd, src_up;
+  double pad0;
+  uint32_t e_lo[2], e_span[2];
+  int32_t n_layers, t_entries, nz, n_slabs;
+  uint64_t root_offset;
+  int64_t dens_off, cur_off;   // element offsets of this instance in the global bins
+  int32_t slab0, pad1;
+  uint8_t tt[kMaxL - 1][2][2]; // transmission table per (interface, direction, spin)
+  uint8_t pad2[4];
+  double T[kMaxT];             // [table][entry]; only the first n_ttables*t_entries used
+};
+// bytes of DevInst that precede the transmission tables
+constexpr int kInstHead = (int)offsetof(DevInst, T);
+
+struct StepArgs {
+  void* z;
+  void* mu;
+  uint32_t* E;
+  uint64_t* uid;
+  uint32_t* flags;
+  uint64_t* ev;                // per-particle event counts (debug) or null
+  const int64_t* slab_base;
+  const int32_t* slab_cap;
+  int32_t* slab_tail;
+  int32_t* slab_dead;
+  const int32_t* slab_inst;
+  const int32_t* slab_k;
+  const DevInst* inst;
+  const int64_t* inj_cum;      // [n_inst][n_steps + 1] cumulative primaries per step
+  const uint32_t* e_edges;
+  uint64_t* dens;
+  int64_t* cur;
+  int64_t* counters;           // [n_steps][kNC]
+  int32_t* queue;              // [n_steps] slab dispenser
+  uint32_t* status;
+  int32_t n_slabs, n_inst, n_ebins, n_steps;
+  int32_t step;
+  uint32_t key0, key1;
+  uint32_t e_min;
+  double dt, h;
+  int32_t tau_exp2, secondaries, debug;
+  int32_t dens_on, cur_on;     // this step deposits density / current
+  int32_t dens_slot, cur_slot;
+  int32_t dens_lds;            // density privatised in LDS (else global atomics)
+  int32_t lds_dens_words;      // u32 words of the LDS density histogram
+  int32_t lds_cur_words;       // u64 words of the LDS current histogram
+  int32_t inst_bytes;          // bytes of DevInst copied into LDS
+};
+
+struct CompactArgs {
+  void* z;
+  void* mu;
+  uint32_t* E;
+  uint64_t* uid;
+  uint32_t* flags;
+  uint64_t* ev;
+  const int64_t* slab_base;
+  int32_t* slab_tail;
+  int32_t* slab_dead;
+  int32_t n_slabs;
+  float frac;
+};
+
+// launchers (pic_kernels.hip)
+hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
+                       hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s);
+hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
+                          double* dout, double* cout, hipStream_t s);
+
+}  // namespace pic

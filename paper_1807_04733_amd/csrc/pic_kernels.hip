@@ -1,0 +1,585 @@
+// Device kernels of the hot-electron particle-in-cell step for gfx950 (CDNA4, wave64).
+//
+// One launch of k_step advances every carrier of every instance by one step of the
+// Strang splitting of arXiv:1807.04733 Eq. (15):
+//   Source(dt/2)     primaries scheduled for this step are created in registers (Eq. 17)
+//   Transport(dt/2)  straight flight, vacuum reflection, stochastic interfaces (Eq. 18)
+//   Scattering(dt)   Monte-Carlo event with p = 1 - exp(-dt/tau_eff) (Eq. 2, Sec. III.A):
+//                    elastic (Eq. 8) or inelastic with an energy-conserving secondary
+//                    (Eqs. 6-7, 19); products below E_min are removed
+//   Transport(dt/2)  for the survivor and the newborn
+//   deposit          density and v*cos(theta) moments (Eqs. 16, 23) into LDS histograms
+//
+// Data layout: structure-of-arrays particle state streamed once per step (z, cos(theta),
+// energy, uid, flags), partitioned into slabs that each belong to one instance.  A slab
+// is processed by one workgroup per step, which appends newborns behind the slab's tail
+// with a wave ballot + one LDS atomic per wave (no global atomics on the append path).
+// Histograms are privatised per workgroup in LDS and merged into the int64 bins with
+// global atomics only for non-zero entries.  All decisions use binary64 arithmetic in
+// the order written here; the file is built with -ffp-contract=off.
+#include "pic_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace pic {
+
+// ------------------------------------------------------------------------- Philox4x32-10
+// Salmon et al. (SC'11).  Two 32x32->64 products per round (v_mad_u64_u32); the key is
+// wave-uniform, so its Weyl schedule stays in scalar registers.
+__device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t m0 = (uint64_t)x0 * 0xD2511F53ull;
+    const uint64_t m1 = (uint64_t)x2 * 0xCD9E8D57ull;
+    const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)m1;
+    x3 = (uint32_t)m0;
+    x0 = y0;
+    x2 = y2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(x0, x1, x2, x3);
+}
+
+// uniform on (0,1) and direction cosine on (-1,1): exact in binary64
+__device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+__device__ __forceinline__ double dircos(uint32_t w) { return ((double)w + 0.5) * 0x1p-31 - 1.0; }
+
+template <typename F>
+__device__ __forceinline__ double to_store(double x) { return (double)(F)x; }
+
+__device__ __forceinline__ int layer_of(uint32_t fl) { return (int)((fl >> kLayerShift) & kLayerMask); }
+
+__device__ __forceinline__ double trans_prob(const DevInst& I, int t, uint32_t E) {
+  const int TE = I.t_entries;
+  const double* tab = I.T + t * TE;
+  if (TE == 1) return tab[0];
+  const double x = ((double)E * 0x1p-30) * I.T_scale;
+  const int k = (int)floor(x);
+  if (k >= TE - 1) return tab[TE - 1];
+  const double f = x - (double)k;
+  return tab[k] + (tab[k + 1] - tab[k]) * f;
+}
+
+struct HitCounts {
+  uint32_t tr, ri, rs;
+};
+
+// Transport over half a step.  The common case (no boundary reached) costs one LDS read
+// of the layer and one of the channel; boundary handling is a rarely taken loop.
+__device__ __forceinline__ void half_push(const DevInst& I, double& z, double& mu, uint32_t& fl,
+                                          uint32_t E, uint32_t lo, uint32_t hi, uint32_t step,
+                                          uint32_t tag, double h, uint32_t k0, uint32_t k1,
+                                          HitCounts& hc, bool& bad) {
+  int l = layer_of(fl);
+  const int s = (int)(fl & kSpinMask);
+  double v = I.chan[l][s].x;
+  double ze = z + (v * mu) * h;
+  double zlo = I.lay[l].x, zhi = I.lay[l].y;
+  if (ze > zhi || ze < zlo) {
+    uint32_t draws = 0;
+    for (int hit = 0;; ++hit) {
+      const bool up = ze > zhi;
+      if (!up && !(ze < zlo)) break;
+      if (hit == kMaxHits) {
+        bad = true;
+        ze = up ? zhi : zlo;
+        break;
+      }
+      const double b = up ? zhi : zlo;
+      const bool outer = up ? (l == I.n_layers - 1) : (l == 0);
+      if (outer) {
+        ze = b - (ze - b);
+        mu = -mu;
+        ++hc.rs;
+        continue;
+      }
+      const int iface = up ? l : l - 1;
+      const int nl = up ? l + 1 : l - 1;
+      const double T = trans_prob(I, I.tt[iface][up ? 0 : 1][s], E);
+      bool go;
+      if (T >= 1.0) {
+        go = true;           // a draw in (0,1) is always below T
+      } else if (T <= 0.0) {
+        go = false;
+      } else {
+        const uint4 w = philox10(lo, hi, step, tag + draws, k0, k1);
+        go = u01(w.x) < T;
+      }
+      ++draws;
+      if (go) {
+        const double vn = I.chan[nl][s].x;
+        const double r = vn / v;
+        ze = b + (ze - b) * r;
+        l = nl;
+        v = vn;
+        zlo = I.lay[l].x;
+        zhi = I.lay[l].y;
+        ++hc.tr;
+      } else {
+        ze = b - (ze - b);
+        mu = -mu;
+        ++hc.ri;
+      }
+    }
+    fl = (fl & ~(kLayerMask << kLayerShift)) | ((uint32_t)l << kLayerShift);
+  }
+  z = ze;
+}
+
+__device__ __forceinline__ int energy_bin(const uint32_t* edges, int n, uint32_t E) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (edges[mid] <= E) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t count_mod(int64_t x, int64_t k, int64_t S) {
+  // number of j in [0, x) with j % S == k
+  return x > k ? (x - 1 - k) / S + 1 : 0;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Deposit one carrier at the end of the step: density per (depth, energy, spin) and the
+// fixed-point current v*cos(theta) per (depth, spin).
+__device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
+                                        unsigned long long* s_cur, const uint32_t* s_edges,
+                                        double z, double mu, uint32_t E, uint32_t fl) {
+  int zb = (int)floor(z * I.inv_dz);
+  zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
+  const int s = (int)(fl & kSpinMask);
+  if (a.dens_on) {
+    const int eb = a.n_ebins > 1 ? energy_bin(s_edges, a.n_ebins, E) : 0;
+    const int idx = (zb * a.n_ebins + eb) * 2 + s;
+    if (a.dens_lds) {
+      atomicAdd(&s_dens[idx], 1u);
+    } else {
+      const int64_t g = I.dens_off + (int64_t)a.dens_slot * I.nz * a.n_ebins * 2 + idx;
+      atomicAdd((unsigned long long*)&a.dens[g], 1ull);
+    }
+  }
+  if (a.cur_on) {
+    const double vm = I.chan[layer_of(fl)][s].x * mu;
+    const long long val = (long long)rint(vm * 4294967296.0);
+    atomicAdd(&s_cur[zb * 2 + s], (unsigned long long)val);
+  }
+}
+
+__device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
+                           unsigned long long* s_cur) {
+  __syncthreads();
+  if (a.dens_on && a.dens_lds) {
+    const int n = I.nz * a.n_ebins * 2;
+    unsigned long long* g =
+        (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.dens_slot * n);
+    for (int b = threadIdx.x; b < n; b += blockDim.x) {
+      const uint32_t v = s_dens[b];
+      if (v) {
+        atomicAdd(&g[b], (unsigned long long)v);
+        s_dens[b] = 0;
+      }
+    }
+  }
+  if (a.cur_on) {
+    const int n = I.nz * 2;
+    unsigned long long* g = (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.cur_slot * n);
+    for (int b = threadIdx.x; b < n; b += blockDim.x) {
+      const unsigned long long v = s_cur[b];
+      if (v) {
+        atomicAdd(&g[b], v);
+        s_cur[b] = 0;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void wave_add(unsigned long long* c, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    if (__lane_id() == leader) atomicAdd(c, (unsigned long long)__popcll(m));
+  }
+}
+
+template <typename F>
+__global__ void __launch_bounds__(256) k_step(StepArgs a) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  uint32_t* s_dens = (uint32_t*)dyn;
+  unsigned long long* s_cur =
+      (unsigned long long*)(dyn + (((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15));
+  __shared__ DevInst s_inst;
+  __shared__ unsigned long long s_cnt[kNC];
+  __shared__ uint32_t s_edges[PIC_MAX_EBINS];
+  __shared__ int s_slab, s_app, s_dead;
+
+  const int tid = threadIdx.x;
+  const int lane = __lane_id();
+  const int wave = tid >> 6;
+  for (int i = tid; i < a.lds_dens_words; i += blockDim.x) s_dens[i] = 0;
+  for (int i = tid; i < a.lds_cur_words; i += blockDim.x) s_cur[i] = 0;
+  for (int i = tid; i < a.n_ebins; i += blockDim.x) s_edges[i] = a.e_edges[i];
+  if (tid < kNC) s_cnt[tid] = 0;
+
+  F* gz = (F*)a.z;
+  F* gmu = (F*)a.mu;
+  const uint32_t step = (uint32_t)a.step;
+  int cur_inst = -1;
+  bool bad = false;
+
+  for (;;) {
+    if (tid == 0) s_slab = atomicAdd(&a.queue[a.step], 1);
+    __syncthreads();
+    const int slab = s_slab;
+    if (slab >= a.n_slabs) break;
+    const int inst = a.slab_inst[slab];
+    if (inst != cur_inst) {
+      if (cur_inst >= 0) flush_bins(a, s_inst, s_dens, s_cur);
+      const uint4* src = (const uint4*)&a.inst[inst];
+      uint4* dst = (uint4*)&s_inst;
+      for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
+      cur_inst = inst;
+    }
+    if (tid == 0) {
+      s_app = 0;
+      s_dead = 0;
+    }
+    __syncthreads();
+    const DevInst& I = s_inst;
+    const int64_t base = a.slab_base[slab];
+    const int cap = a.slab_cap[slab];
+    const int tail0 = a.slab_tail[slab];
+    const int64_t kk = a.slab_k[slab];
+    const int64_t S = I.n_slabs;
+    const int64_t* cum = a.inj_cum + (int64_t)inst * (a.n_steps + 1);
+    const int64_t f0 = count_mod(cum[step], kk, S);
+    const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
+    const int total = tail0 + n_inj;
+
+    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
+      const int t = tb + lane;
+      const bool have = t < total;
+      const bool from_soa = have && t < tail0;
+      const bool is_new = have && !from_soa;
+      const int64_t gi = base + t;
+      double z = 0.0, mu = 0.0;
+      uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
+      uint64_t evp = 0;
+      if (from_soa) {
+        fl = a.flags[gi];
+        if (!(fl & kDead)) {
+          z = (double)gz[gi];
+          mu = (double)gmu[gi];
+          E = a.E[gi];
+          const uint64_t u = a.uid[gi];
+          lo = (uint32_t)u;
+          hi = (uint32_t)(u >> 32);
+          if (a.debug) evp = a.ev[gi];
+        }
+      } else if (is_new) {
+        // Source term: one primary per root, Eq. (17)
+        const int64_t j = kk + S * (f0 + (t - tail0));
+        const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
+        const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
+        double z0;
+        if (I.src_lambda > 0.0)
+          z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
+        else
+          z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
+        z = to_store<F>(z0);
+        mu = to_store<F>(dircos(w.y));
+        const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
+        E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
+        int l = 0;
+        for (int q = 1; q < I.n_layers; ++q)
+          if (I.lay[q].x <= z) l = q;
+        fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift);
+        lo = root;
+        hi = 0;
+      }
+      const bool alive0 = !(fl & kDead);
+      bool died = false, child = false;
+      uint32_t dirty = 0;  // 1: mu, 2: E, 4: flags
+      double cz = 0.0, cmu = 0.0;
+      uint32_t cE = 0, cfl = 0, clo = 0, chi = 0;
+      uint64_t cevp = 0;
+      HitCounts hc{0, 0, 0}, hcc{0, 0, 0};
+      if (alive0) {
+        const double mu_in = mu;
+        const uint32_t fl_in = fl;
+        half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad);
+        // ---- scattering over the full step, at the mid-step state
+        const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
+        const int l = layer_of(fl);
+        const int s = (int)(fl & kSpinMask);
+        const double E_ev = (double)E * 0x1p-30;
+        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
+        const double itel = I.lay[l].z;
+        const double rate = Ek * I.chan[l][s].y + itel;
+        const double x = a.dt * rate;
+        const double u0 = u01(w.x);
+        // p = 1 - exp(-x) < x, so u0 >= x rejects without the transcendental
+        bool event = false;
+        if (u0 < x) event = u0 < -expm1(-x);
+        if (event) {
+          if (a.debug) evp += 1ull;
+          const bool elastic = itel > 0.0 && u01(w.y) < itel / rate;
+          mu = to_store<F>(dircos(w.z));
+          dirty |= 1u;
+          if (elastic) {
+            atomicAdd(&s_cnt[PIC_C_EV_EL], 1ull);
+          } else {
+            atomicAdd(&s_cnt[PIC_C_EV_EE], 1ull);
+            const uint32_t E1 = __umulhi(w.w, E);
+            const uint32_t E2 = E - E1;
+            E = E1;
+            dirty |= 2u;
+            if (a.secondaries) {
+              if (E2 >= a.e_min) {
+                const uint4 sw = philox10(lo, hi, step, kTagSpawn, a.key0, a.key1);
+                child = true;
+                cz = z;
+                cmu = to_store<F>(dircos(sw.x));
+                cE = E2;
+                const uint32_t cs = u01(sw.y) < I.lay[l].w ? 0u : 1u;
+                uint32_t gen = (fl >> kGenShift) & kGenMask;
+                gen = gen < 255u ? gen + 1u : 255u;
+                cfl = cs | ((uint32_t)l << kLayerShift) | (gen << kGenShift);
+                uint32_t lin = sw.z;
+                if (lin == 0u || lin == hi) {
+                  lin = sw.w | 1u;
+                  if (lin == hi) lin ^= 2u;
+                }
+                clo = lo;
+                chi = lin;
+                if (a.debug) evp += 1ull << 48;
+                atomicAdd(&s_cnt[PIC_C_SPAWNED], 1ull);
+              } else {
+                atomicAdd(&s_cnt[PIC_C_SEC_ABSORBED], 1ull);
+                atomicAdd(&s_cnt[PIC_C_E_ABSORBED], (unsigned long long)E2);
+              }
+            }
+            if (E1 < a.e_min) {
+              died = true;
+              atomicAdd(&s_cnt[PIC_C_ABSORBED], 1ull);
+              atomicAdd(&s_cnt[PIC_C_E_ABSORBED], (unsigned long long)E1);
+            }
+          }
+        }
+        if (!died) {
+          half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
+          z = to_store<F>(z);
+          deposit(a, I, s_dens, s_cur, s_edges, z, mu, E, fl);
+        } else {
+          z = to_store<F>(z);
+          fl |= kDead;
+        }
+        if (mu != mu_in) dirty |= 1u;
+        if (fl != fl_in) dirty |= 4u;
+        if (child) {
+          half_push(I, cz, cmu, cfl, cE, clo, chi, step, kTagHalf2, a.h, a.key0, a.key1, hcc, bad);
+          cz = to_store<F>(cz);
+          deposit(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl);
+        }
+      }
+      if (hc.tr + hcc.tr) atomicAdd(&s_cnt[PIC_C_TRANSMIT], (unsigned long long)(hc.tr + hcc.tr));
+      if (hc.ri + hcc.ri) atomicAdd(&s_cnt[PIC_C_REFL_IF], (unsigned long long)(hc.ri + hcc.ri));
+      if (hc.rs + hcc.rs) atomicAdd(&s_cnt[PIC_C_REFL_SURF], (unsigned long long)(hc.rs + hcc.rs));
+      if (a.debug) {
+        // packed per-particle counts: events | transmissions << 16 | reflections << 32 |
+        // spawns << 48
+        evp += ((uint64_t)hc.tr << 16) + ((uint64_t)(hc.ri + hc.rs) << 32);
+        cevp = ((uint64_t)hcc.tr << 16) + ((uint64_t)(hcc.ri + hcc.rs) << 32);
+      }
+      wave_add(&s_cnt[PIC_C_INJECTED], is_new);
+      wave_add(&s_cnt[PIC_C_ALIVE], alive0 && !died);
+      wave_add(&s_cnt[PIC_C_ALIVE], child);
+
+      // ---- append the new primary (always, so that an absorbed one leaves its record)
+      // and the newborn behind the slab's tail: one LDS atomic per wave
+      const uint64_t ma = __ballot(is_new);
+      const uint64_t mb = __ballot(child);
+      const int na = __popcll(ma), nb = __popcll(mb);
+      int off = 0;
+      if (na + nb) {
+        const int leader = __ffsll((unsigned long long)(ma | mb)) - 1;
+        if (lane == leader) off = atomicAdd(&s_app, na + nb);
+        off = __shfl(off, leader);
+      }
+      const uint64_t below = lanes_below();
+      if (from_soa && alive0) {
+        gz[gi] = (F)z;
+        if (dirty & 1u) gmu[gi] = (F)mu;
+        if (dirty & 2u) a.E[gi] = E;
+        if (dirty & 4u) a.flags[gi] = fl;
+        if (a.debug) a.ev[gi] = evp;
+      }
+      if (is_new) {
+        const int pos = tail0 + off + __popcll(ma & below);
+        if (pos < cap) {
+          const int64_t g = base + pos;
+          gz[g] = (F)z;
+          gmu[g] = (F)mu;
+          a.E[g] = E;
+          a.uid[g] = (uint64_t)lo | ((uint64_t)hi << 32);
+          a.flags[g] = fl;
+          if (a.debug) a.ev[g] = evp;
+        } else {
+          atomicOr(a.status, kStOverflow);
+        }
+      }
+      if (child) {
+        const int pos = tail0 + off + na + __popcll(mb & below);
+        if (pos < cap) {
+          const int64_t g = base + pos;
+          gz[g] = (F)cz;
+          gmu[g] = (F)cmu;
+          a.E[g] = cE;
+          a.uid[g] = (uint64_t)clo | ((uint64_t)chi << 32);
+          a.flags[g] = cfl;
+          if (a.debug) a.ev[g] = cevp;
+        } else {
+          atomicOr(a.status, kStOverflow);
+        }
+      }
+      const uint64_t md = __ballot(died);
+      if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nt = tail0 + s_app;
+      if (nt > cap) nt = cap;
+      a.slab_tail[slab] = nt;
+      a.slab_dead[slab] += s_dead;
+    }
+  }
+  if (cur_inst >= 0) flush_bins(a, s_inst, s_dens, s_cur);
+  if (bad) atomicOr(a.status, kStHits);
+  __syncthreads();
+  if (tid < kNC && s_cnt[tid])
+    atomicAdd((unsigned long long*)&a.counters[(int64_t)a.step * kNC + tid], s_cnt[tid]);
+}
+
+// In-place compaction of slabs whose tombstones exceed a fraction of their tail.  One
+// workgroup per slab walks it tile by tile: every lane loads its slot, a workgroup scan
+// of the live lanes gives the destination, and the stores follow a barrier, so a
+// destination (always <= its source) is never overwritten before it has been read.
+template <typename F>
+__global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
+  __shared__ int s_w[16];
+  const int slab = blockIdx.x;
+  const int tail = a.slab_tail[slab];
+  const int dead = a.slab_dead[slab];
+  if (tail == 0 || !((float)dead > a.frac * (float)tail)) return;
+  const int64_t base = a.slab_base[slab];
+  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  F* gz = (F*)a.z;
+  F* gmu = (F*)a.mu;
+  int out = 0;
+  for (int tb = 0; tb < tail; tb += blockDim.x) {
+    const int t = tb + tid;
+    const bool have = t < tail;
+    uint32_t fl = have ? a.flags[base + t] : kDead;
+    const bool keep = !(fl & kDead);
+    F z = 0, mu = 0;
+    uint32_t E = 0;
+    uint64_t u = 0, ev = 0;
+    if (keep) {
+      z = gz[base + t];
+      mu = gmu[base + t];
+      E = a.E[base + t];
+      u = a.uid[base + t];
+      if (a.ev) ev = a.ev[base + t];
+    }
+    const uint64_t m = __ballot(keep);
+    if (lane == 0) s_w[wave] = __popcll(m);
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int c = s_w[w];
+      woff += w < wave ? c : 0;
+      tot += c;
+    }
+    if (keep) {
+      const int64_t d = base + out + woff + __popcll(m & lanes_below());
+      gz[d] = z;
+      gmu[d] = mu;
+      a.E[d] = E;
+      a.uid[d] = u;
+      a.flags[d] = fl;
+      if (a.ev) a.ev[d] = ev;
+    }
+    out += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.slab_tail[slab] = out;
+    a.slab_dead[slab] = 0;
+  }
+}
+
+__global__ void k_fill32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
+                          double* dout, double* cout) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd || i < nc;
+       i += stride) {
+    if (dout && i < nd) dout[i] = (double)dens[i];
+    if (cout && i < nc) cout[i] = (double)cur[i] * 0x1p-32;
+  }
+}
+
+hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
+                       hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_step<double>, dim3(grid), dim3(block), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_step<float>, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s) {
+  if (a.n_slabs <= 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL(k_compact<double>, dim3(a.n_slabs), dim3(block), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_compact<float>, dim3(a.n_slabs), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
+                          double* dout, double* cout, hipStream_t s) {
+  const int64_t n = nd > nc ? nd : nc;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, s, dens, nd, cur, nc,
+                     dout, cout);
+  return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,254 @@
+"""Python binding of libpic: argument marshalling around the C ABI.
+
+Every step of the particle update runs in the HIP kernels of libpic.so; PyTorch only
+provides the device workspace, the output tensors and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+
+
+def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
+                capacity_factor: float = 0.0):
+    """Translate a workloads.Problem into the C structs (returns config and a keep-alive)."""
+    insts = (_abi.PicInstance * len(problem.instances))()
+    for i, it in enumerate(problem.instances):
+        s = insts[i]
+        L = it.n_layers
+        if L > _abi.MAX_LAYERS or it.n_channels > _abi.MAX_CHANNELS:
+            raise ValueError("instance exceeds the library's table limits")
+        s.n_layers, s.n_channels = L, it.n_channels
+        s.n_ttables, s.t_entries = it.n_ttables, it.t_entries
+        for l in range(L + 1):
+            s.z_bound[l] = float(it.z_bound[l])
+        for l in range(L):
+            s.ch_of[l][0], s.ch_of[l][1] = int(it.ch_of[l, 0]), int(it.ch_of[l, 1])
+            s.inv_tau_el[l] = float(it.inv_tau_el[l])
+            s.P0[l] = float(it.P0[l])
+        for c in range(it.n_channels):
+            s.v[c] = float(it.v[c])
+            s.inv_tau0[c] = float(it.inv_tau0[c])
+        for k in range(L - 1):
+            for d in range(2):
+                for sp in range(2):
+                    s.tt_of[k][d][sp] = int(it.tt_of[k, d, sp])
+        for t in range(it.n_ttables):
+            for e in range(it.t_entries):
+                s.T[t][e] = float(it.T[t, e])
+        s.T_scale = float(it.T_scale)
+        s.src_z_lo, s.src_z_hi = float(it.src_z_lo), float(it.src_z_hi)
+        s.src_lambda, s.src_cd = float(it.src_lambda), float(it.src_cd)
+        s.src_up_frac = float(it.src_up_frac)
+        for sp in range(2):
+            s.src_e_lo[sp] = int(it.src_e_lo[sp])
+            s.src_e_span[sp] = int(it.src_e_span[sp])
+        s.n_primaries = int(it.n_primaries)
+        s.root_offset = int(it.root_offset)
+        s.nz = int(it.nz)
+        s.inv_dz = float(it.inv_dz)
+    cfg = _abi.PicConfig()
+    cfg.n_instances = len(problem.instances)
+    cfg.inst = insts
+    cfg.seed = int(problem.seed)
+    cfg.dt = float(problem.dt)
+    cfg.n_steps = int(problem.n_steps)
+    cfg.tau_exp = int(problem.tau_exp)
+    cfg.e_min_fx = int(problem.e_min_fx)
+    flags = 0
+    if problem.state_fp64:
+        flags |= _abi.F_STATE_FP64
+    if problem.secondaries:
+        flags |= _abi.F_SECONDARIES
+    if debug:
+        flags |= _abi.F_DEBUG
+    cfg.flags = flags
+    if problem.n_ebins > _abi.MAX_EBINS:
+        raise ValueError("too many energy bins")
+    cfg.n_ebins = problem.n_ebins
+    for k, e in enumerate(problem.e_edges):
+        cfg.e_edges[k] = int(e)
+    cfg.dens_stride = int(problem.dens_stride)
+    cfg.cur_stride = int(problem.cur_stride)
+    cfg.slab_primaries = int(slab_primaries)
+    cfg.capacity_factor = float(capacity_factor)
+    return cfg, insts
+
+
+def workspace_bytes(problem, **kw) -> int:
+    cfg, keep = make_config(problem, **kw)
+    n = C.c_int64()
+    _abi.check(_abi.load().pic_workspace_size(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+class PicSim:
+    """One simulation context on a GPU (a thin owner of the workspace and the handle)."""
+
+    def __init__(self, problem, *, device="cuda", debug: bool = False,
+                 slab_primaries: int = 0, capacity_factor: float = 0.0, stream=None,
+                 tuning: Optional[dict] = None):
+        import torch
+
+        self.problem = problem
+        self.lib = _abi.load()
+        self.device = torch.device(device)
+        self._cfg, self._keep = make_config(problem, debug=debug,
+                                            slab_primaries=slab_primaries,
+                                            capacity_factor=capacity_factor)
+        n = C.c_int64()
+        _abi.check(self.lib.pic_workspace_size(C.byref(self._cfg), C.byref(n)))
+        self.ws_bytes = n.value
+        # a stream of our own (default priority): the legacy NULL stream cannot be
+        # captured into a graph
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(self.stream):
+            raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        shift = (-raw.data_ptr()) % 256
+        if shift % 8:
+            raise RuntimeError("workspace allocation is not 8-byte aligned")
+        self._raw = raw
+        self.ws = raw[shift:shift + self.ws_bytes]
+        self.handle = C.c_void_p()
+        _abi.check(self.lib.pic_init(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()),
+                                     C.c_int64(self.ws_bytes),
+                                     C.c_void_p(self.stream.cuda_stream),
+                                     C.byref(self.handle)))
+        sched = np.ascontiguousarray(np.stack([it.sched for it in problem.instances]), np.int64)
+        _abi.check(self.lib.pic_inject(self.handle, sched.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.layout = _abi.PicLayout()
+        _abi.check(self.lib.pic_layout_of(self.handle, C.byref(self.layout)))
+        if tuning:
+            self.set_tuning(**tuning)
+
+    # ---------------------------------------------------------------- driving
+    def step(self, n: Optional[int] = None):
+        if n is None:
+            n = self.problem.n_steps
+        _abi.check(self.lib.pic_step(self.handle, int(n)))
+
+    def reset(self):
+        _abi.check(self.lib.pic_reset(self.handle))
+
+    def tuning(self) -> dict:
+        t = _abi.PicTuning()
+        _abi.check(self.lib.pic_get_tuning(self.handle, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = _abi.PicTuning(**cur)
+        _abi.check(self.lib.pic_set_tuning(self.handle, C.byref(t)))
+
+    def autotune(self, trial_steps: int = 20) -> dict:
+        t = _abi.PicTuning()
+        _abi.check(self.lib.pic_autotune(self.handle, int(trial_steps), C.byref(t)))
+        return {k: getattr(t, k) for k, _ in t._fields_}
+
+    def counters(self) -> np.ndarray:
+        out = np.zeros((self.problem.n_steps, _abi.NCOUNTERS), np.int64)
+        _abi.check(self.lib.pic_counters(self.handle, out.ctypes.data_as(C.POINTER(C.c_int64))))
+        return out
+
+    def deposit(self):
+        """Binary64 bins per instance: (dens list, cur list) of device tensors."""
+        import torch
+
+        lay = self.layout
+        with torch.cuda.stream(self.stream):
+            d = torch.empty(lay.dens_len, dtype=torch.float64, device=self.device)
+            c = torch.empty(lay.cur_len, dtype=torch.float64, device=self.device)
+            _abi.check(self.lib.pic_deposit(self.handle, C.c_void_p(d.data_ptr()),
+                                            C.c_void_p(c.data_ptr())))
+        self.stream.synchronize()
+        dens, cur = [], []
+        od = oc = 0
+        for i in range(len(self.problem.instances)):
+            sd = self.problem.dens_shape(i)
+            sc = self.problem.cur_shape(i)
+            nd, nc = int(np.prod(sd)), int(np.prod(sc))
+            dens.append(d[od:od + nd].view(sd))
+            cur.append(c[oc:oc + nc].view(sc))
+            od += nd
+            oc += nc
+        return dens, cur
+
+    def int_bins(self):
+        """The raw integer bins (uint64 counts, int64 2^-32 nm/fs) as host arrays."""
+        import torch
+
+        self.stream.synchronize()
+        lay = self.layout
+        d = self.ws[lay.off_dens:lay.off_dens + 8 * lay.dens_len].view(torch.int64)
+        c = self.ws[lay.off_cur:lay.off_cur + 8 * lay.cur_len].view(torch.int64)
+        d = d.cpu().numpy().view(np.uint64)
+        c = c.cpu().numpy()
+        dens, cur = [], []
+        od = oc = 0
+        for i in range(len(self.problem.instances)):
+            sd, sc = self.problem.dens_shape(i), self.problem.cur_shape(i)
+            nd, nc = int(np.prod(sd)), int(np.prod(sc))
+            dens.append(d[od:od + nd].reshape(sd))
+            cur.append(c[oc:oc + nc].reshape(sc))
+            od += nd
+            oc += nc
+        return dens, cur
+
+    def particles(self, include_dead: bool = True) -> dict:
+        """Copy the particle state out of the workspace (for inspection and tests)."""
+        import torch
+
+        self.stream.synchronize()
+        lay = self.layout
+        ws = self.ws
+        ns = lay.n_slabs
+
+        def arr(off, n, dt):
+            nb = n * torch.tensor([], dtype=dt).element_size()
+            return ws[off:off + nb].view(dt)
+
+        base = arr(lay.off_slab_base, ns, torch.int64).cpu().numpy()
+        tail = arr(lay.off_slab_tail, ns, torch.int32).cpu().numpy()
+        inst = arr(lay.off_slab_inst, ns, torch.int32).cpu().numpy()
+        idx = np.concatenate([np.arange(b, b + t, dtype=np.int64) for b, t in zip(base, tail)]
+                             + [np.zeros(0, np.int64)])
+        slab_of = np.repeat(np.arange(ns), tail)
+        fdt = torch.float64 if lay.state_bytes == 8 else torch.float32
+        cap = lay.capacity
+        ti = torch.from_numpy(idx).to(self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        z = arr(lay.off_z, cap, fdt)[ti].double().cpu().numpy()
+        mu = arr(lay.off_mu, cap, fdt)[ti].double().cpu().numpy()
+        E = arr(lay.off_E, cap, torch.int32)[ti].cpu().numpy().view(np.uint32)
+        uid = arr(lay.off_uid, cap, torch.int64)[ti].cpu().numpy().view(np.uint64)
+        fl = arr(lay.off_flags, cap, torch.int32)[ti].cpu().numpy().view(np.uint32)
+        out = dict(z=z, mu=mu, E=E, uid=uid,
+                   spin=(fl & 1).astype(np.int32),
+                   layer=((fl >> np.uint32(lay.flags_layer_shift)) & np.uint32(0xF)).astype(np.int32),
+                   gen=((fl >> np.uint32(lay.flags_gen_shift)) & np.uint32(0xFF)).astype(np.int32),
+                   dead=((fl & np.uint32(lay.flags_dead_bit)) != 0),
+                   inst=inst[slab_of].astype(np.int32))
+        if lay.off_ev >= 0:
+            ev = arr(lay.off_ev, cap, torch.int64)[ti].cpu().numpy().view(np.uint64)
+            out["ev"] = np.stack([(ev >> np.uint64(16 * k)) & np.uint64(0xFFFF)
+                                  for k in range(4)], axis=1).astype(np.int32)
+        if not include_dead:
+            keep = ~out["dead"]
+            out = {k: v[keep] for k, v in out.items()}
+        return out
+
+    def close(self):
+        if self.handle:
+            self.lib.pic_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

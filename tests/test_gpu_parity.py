@@ -1,0 +1,162 @@
+"""Device path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Acceptance: per-particle final state and event counts (joined on uid) identical for
+>= 99.99 % of particles; the integer bins identical, and the binary64 bins within
+1e-5 relative L1.  Sizes span several slabs, several waves per slab and ragged tails.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import compare_records, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_both(prob, oracle_mod, *, debug=True, tuning=None, slab_primaries=0, records=True):
+    from paper_1807_04733_amd import PicSim
+    _say(f"[parity] {prob.name or 'problem'}: {prob.n_primaries} primaries, "
+         f"{len(prob.instances)} inst, {prob.n_steps} steps, debug={debug}, tuning={tuning}")
+    sim = PicSim(prob, debug=debug, slab_primaries=slab_primaries, tuning=tuning)
+    sim.step()
+    cnt = sim.counters()
+    dens, cur = sim.int_bins()
+    fd, fc = sim.deposit()
+    fd = [x.cpu().numpy() for x in fd]
+    fc = [x.cpu().numpy() for x in fc]
+    parts = sim.particles() if records else None
+    sim.close()
+    ref = oracle_mod.run(prob, records=records)
+    return dict(cnt=cnt, dens=dens, cur=cur, fd=fd, fc=fc, parts=parts), ref
+
+
+def assert_parity(dev, ref, prob, *, exact_bins=True):
+    fp64 = prob.state_fp64
+    if dev["parts"] is not None:
+        r = compare_records(dev["parts"], ref.records, fp64, z_tol=1e-9 if fp64 else 0.0)
+        _say(f"[parity] joined {r['joined']} / dev {r['n_dev']} / ref {r['n_ref']}, "
+             f"match {r['frac']:.6f}")
+        assert r["joined"] >= 0.999 * r["n_ref"]
+        assert r["frac"] >= 0.9999, r["bad"]
+    for i in range(len(prob.instances)):
+        assert rel_l1(dev["fd"][i], ref.dens[i]) <= 1e-5
+        assert rel_l1(dev["fc"][i], ref.cur_float(i)) <= 1e-5
+        if exact_bins:
+            assert np.array_equal(dev["dens"][i], ref.dens[i])
+            assert np.array_equal(dev["cur"][i], ref.cur[i])
+    if exact_bins:
+        assert np.array_equal(dev["cnt"], ref.counters)
+
+
+def test_bilayer_fp64(torch_gpu, oracle_mod):
+    prob = W.config0(n_primaries=5000, n_steps=120)
+    dev, ref = run_both(prob, oracle_mod)
+    assert_parity(dev, ref, prob)
+
+
+@pytest.mark.parametrize("parallel", [True, False])
+def test_spin_valve_fp32(torch_gpu, oracle_mod, parallel):
+    prob = W.config1(parallel=parallel, n_primaries=7001, n_steps=160)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=1024)
+    assert_parity(dev, ref, prob)
+
+
+def test_elastic_and_constant_tau(torch_gpu, oracle_mod):
+    prob = W.homogeneous(thickness=37.5, n_primaries=3333, n_steps=90, tau0=25.0, tau_el=30.0,
+                         tau_exp=0, e_edges=W.energy_edges(0.1, 2.0), state_fp64=False,
+                         src=(0.0, 37.5))
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=700)
+    assert_parity(dev, ref, prob)
+    assert ref.counters[:, 2].sum() > 1000     # elastic events happened
+
+
+def test_batched_instances(torch_gpu, oracle_mod):
+    prob = W.config2(n_instances=6, n_steps=70, prim_lo=50, prim_hi=3000)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=512)
+    assert_parity(dev, ref, prob)
+
+
+def test_energy_tables_and_gaussian_pump(torch_gpu, oracle_mod):
+    prob = W.config4(n_instances=3, primaries_per_instance=1500, n_steps=400)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=400)
+    assert_parity(dev, ref, prob)
+    assert (ref.counters[:, 0] > 0).sum() > 50    # injection spread over many steps
+
+
+def test_edge_cases(torch_gpu, oracle_mod):
+    # an empty instance, a one-primary instance and a ragged one, single step
+    insts = [W.make_instance(W.bilayer(), n_primaries=n, n_steps=1) for n in (0, 1, 65)]
+    prob = W.Problem(W.with_root_offsets(insts), seed=9, dt=1.0, n_steps=1)
+    dev, ref = run_both(prob, oracle_mod)
+    assert_parity(dev, ref, prob)
+    # no secondaries (the paper's third case)
+    prob = W.config0(n_primaries=999, n_steps=60)
+    prob.secondaries = False
+    dev, ref = run_both(prob, oracle_mod)
+    assert_parity(dev, ref, prob)
+
+
+def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
+    prob = W.config1(parallel=True, n_primaries=6000, n_steps=120)
+    prob.dens_stride = 3
+    ref = oracle_mod.run(prob)
+    for tuning in ({"block": 64, "grid": 7, "compact_every": 0},
+                   {"block": 128, "grid": 1000, "compact_every": 1, "compact_frac": 0.0},
+                   {"block": 256, "grid": 64, "compact_every": 5, "use_graph": 0}):
+        from paper_1807_04733_amd import PicSim
+        _say(f"[parity] launch shape {tuning}")
+        sim = PicSim(prob, slab_primaries=1000, tuning=tuning)
+        sim.step(50)
+        sim.step(70)
+        dens, cur = sim.int_bins()
+        cnt = sim.counters()
+        sim.close()
+        assert np.array_equal(dens[0], ref.dens[0])
+        assert np.array_equal(cur[0], ref.cur[0])
+        assert np.array_equal(cnt, ref.counters)
+
+
+def test_capacity_overflow_is_reported(torch_gpu):
+    from paper_1807_04733_amd import PicSim, PicError
+    prob = W.config0(n_primaries=2000, n_steps=100)
+    sim = PicSim(prob, capacity_factor=1.05)
+    sim.step()
+    with pytest.raises(PicError) as e:
+        sim.counters()
+    assert e.value.code == 3
+    sim.close()
+
+
+def test_reset_replays_identically(torch_gpu):
+    from paper_1807_04733_amd import PicSim
+    prob = W.config1(n_primaries=4000, n_steps=50)
+    sim = PicSim(prob)
+    sim.step()
+    a = sim.int_bins()
+    sim.reset()
+    sim.step()
+    b = sim.int_bins()
+    sim.close()
+    assert all(np.array_equal(x, y) for x, y in zip(a[0] + a[1], b[0] + b[1]))
