@@ -160,6 +160,11 @@ pic_status pic_inject(pic_ctx* ctx, const int64_t* sched);
 /* Enqueue n steps (the next ones after those already run). */
 pic_status pic_step(pic_ctx* ctx, int32_t n);
 
+/* Enqueue one compaction pass now (slabs whose dead slots exceed
+ * pic_tuning.compact_frac of their tail are compacted in place).  pic_step() already
+ * runs it every compact_every steps; this entry lets a caller time it separately. */
+pic_status pic_compact(pic_ctx* ctx);
+
 /* Convert the integer bins to binary64: dens_out [sum_i n_dslots*nz_i*NE*2] particle
  * counts and cur_out [sum_i n_cslots*nz_i*2] sum of v*cos(theta) in nm/fs; instances are
  * concatenated in order.  Device pointers (either may be NULL).  Enqueued, async. */

@@ -24,7 +24,7 @@ NCOUNTERS = len(COUNTER_NAMES)
 STATUS = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ENOMEM", 3: "PIC_ECAPACITY", 4: "PIC_EHIP",
           5: "PIC_ESTATE"}
 
-EXPORTS = ("pic_workspace_size", "pic_init", "pic_inject", "pic_step", "pic_deposit",
+EXPORTS = ("pic_workspace_size", "pic_init", "pic_inject", "pic_step", "pic_compact", "pic_deposit",
            "pic_backward", "pic_counters", "pic_reset", "pic_set_tuning", "pic_get_tuning",
            "pic_layout_of", "pic_autotune", "pic_destroy", "pic_last_error")
 
@@ -100,6 +100,7 @@ def load():
         "pic_init": ([P(PicConfig), vp, C.c_int64, vp, P(vp)], C.c_int),
         "pic_inject": ([vp, P(C.c_int64)], C.c_int),
         "pic_step": ([vp, C.c_int32], C.c_int),
+        "pic_compact": ([vp], C.c_int),
         "pic_deposit": ([vp, vp, vp], C.c_int),
         "pic_backward": ([vp, vp, vp, vp, C.c_int32], C.c_int),
         "pic_counters": ([vp, P(C.c_int64)], C.c_int),

@@ -260,7 +260,8 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.dens_slot = n / c->cfg.dens_stride;
   a.cur_slot = n / c->cfg.cur_stride;
   a.dens_lds = c->dens_lds;
-  a.lds_dens_words = c->lds_dens_words;
+  // the density histogram occupies LDS only on the steps that deposit density
+  a.lds_dens_words = a.dens_on ? c->lds_dens_words : 0;
   a.lds_cur_words = c->lds_cur_words;
   a.inst_bytes = c->inst_bytes;
   return a;
@@ -290,7 +291,8 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
   grid = std::max(1, std::min(grid, n_slabs));
   for (int s = start; s < start + n; ++s) {
     StepArgs a = step_args(c, s);
-    HIP_TRY(launch_step(a, fp64, grid, c->tune.block, c->lds_bytes, c->stream));
+    const size_t lds = (((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15) + (size_t)a.lds_cur_words * 8;
+    HIP_TRY(launch_step(a, fp64, grid, c->tune.block, lds, c->stream));
     if (c->tune.compact_every > 0 && !c->plan.debug && (s + 1) % c->tune.compact_every == 0 &&
         s + 1 < c->cfg.n_steps) {
       CompactArgs ca = compact_args(c);
@@ -314,6 +316,12 @@ pic_status upload_tables(pic_ctx* c) {
       for (int s = 0; s < 2; ++s)
         D.chan[l][s] = make_double2(I.v[I.ch_of[l][s]], I.inv_tau0[I.ch_of[l][s]]);
     }
+    for (int l = 0; l < I.n_layers; ++l)
+      for (int s = 0; s < 2; ++s) {
+        const double v = I.v[I.ch_of[l][s]];
+        D.ratio[l][s][0] = l + 1 < I.n_layers ? I.v[I.ch_of[l + 1][s]] / v : 1.0;
+        D.ratio[l][s][1] = l > 0 ? I.v[I.ch_of[l - 1][s]] / v : 1.0;
+      }
     D.T_scale = I.T_scale;
     D.inv_dz = I.inv_dz;
     D.src_lo = I.src_z_lo;
@@ -484,6 +492,14 @@ pic_status pic_step(pic_ctx* c, int32_t n) {
     if (st != PIC_OK) return st;
   }
   c->step += n;
+  return PIC_OK;
+}
+
+pic_status pic_compact(pic_ctx* c) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  if (c->plan.debug) return PIC_OK;  // debug runs keep every record in place
+  CompactArgs ca = compact_args(c);
+  HIP_TRY(launch_compact(ca, c->plan.state_bytes == 8, c->tune.block, c->stream));
   return PIC_OK;
 }
 

@@ -36,6 +36,7 @@ constexpr uint32_t kStHits = 2u;
 struct alignas(32) DevInst {
   double4 lay[kMaxL];          // (z_lo, z_hi, 1/tau_el, P(up) of a secondary)
   double2 chan[kMaxL][2];      // per (layer, spin): (speed, 1/tau0)
+  double ratio[kMaxL][2][2];   // per (layer, spin, direction +z/-z): v_next / v_this
   double T_scale, inv_dz;
   double src_lo, src_hi, src_lambda, src_cd, src_up;
   double pad0;

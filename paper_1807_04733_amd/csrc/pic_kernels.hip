@@ -26,20 +26,37 @@ namespace pic {
 // ------------------------------------------------------------------------- Philox4x32-10
 // Salmon et al. (SC'11).  Two 32x32->64 products per round (v_mad_u64_u32); the key is
 // wave-uniform, so its Weyl schedule stays in scalar registers.
+// Three-input XOR with the round key in a scalar register: gfx950's three-operand
+// bitwise op with truth table 0x96 (odd parity), one VALU op instead of two.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+// Scalar add for the Weyl key schedule; volatile so that the 20 round keys are
+// recomputed per call on the scalar unit instead of being kept live in SGPRs.
+__device__ __forceinline__ uint32_t key_step(uint32_t k, uint32_t w) {
+  uint32_t r;
+  asm volatile("s_add_u32 %0, %1, %2" : "=s"(r) : "s"(k), "s"(w) : "scc");
+  return r;
+}
+
 __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t m0 = (uint64_t)x0 * 0xD2511F53ull;
     const uint64_t m1 = (uint64_t)x2 * 0xCD9E8D57ull;
-    const uint32_t y0 = (uint32_t)(m1 >> 32) ^ x1 ^ k0;
-    const uint32_t y2 = (uint32_t)(m0 >> 32) ^ x3 ^ k1;
+    const uint32_t y0 = xor3_key((uint32_t)(m1 >> 32), x1, k0);
+    const uint32_t y2 = xor3_key((uint32_t)(m0 >> 32), x3, k1);
     x1 = (uint32_t)m1;
     x3 = (uint32_t)m0;
     x0 = y0;
     x2 = y2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
+    if (r < 9) {
+      k0 = key_step(k0, 0x9E3779B9u);
+      k1 = key_step(k1, 0xBB67AE85u);
+    }
   }
   return make_uint4(x0, x1, x2, x3);
 }
@@ -76,7 +93,7 @@ __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& m
                                           HitCounts& hc, bool& bad) {
   int l = layer_of(fl);
   const int s = (int)(fl & kSpinMask);
-  double v = I.chan[l][s].x;
+  const double v = I.chan[l][s].x;
   double ze = z + (v * mu) * h;
   double zlo = I.lay[l].x, zhi = I.lay[l].y;
   if (ze > zhi || ze < zlo) {
@@ -111,11 +128,10 @@ __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& m
       }
       ++draws;
       if (go) {
-        const double vn = I.chan[nl][s].x;
-        const double r = vn / v;
+        // speed ratio new/old layer, divided once on the host (same IEEE quotient)
+        const double r = I.ratio[l][s][up ? 0 : 1];
         ze = b + (ze - b) * r;
         l = nl;
-        v = vn;
         zlo = I.lay[l].x;
         zhi = I.lay[l].y;
         ++hc.tr;
@@ -152,33 +168,44 @@ __device__ __forceinline__ uint64_t lanes_below() {
 
 // Deposit one carrier at the end of the step: density per (depth, energy, spin) and the
 // fixed-point current v*cos(theta) per (depth, spin).
+// Compile-time launch modes of the step kernel.
+constexpr int kModeDebug = 1;       // keep per-particle event counts
+constexpr int kModeDensLds = 2;     // this step deposits density into LDS
+constexpr int kModeDensGlobal = 4;  // this step deposits density with global atomics
+constexpr int kModeCur = 8;         // this step deposits the current
+
+template <int MODE>
 __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
                                         unsigned long long* s_cur, const uint32_t* s_edges,
                                         double z, double mu, uint32_t E, uint32_t fl) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
-  if (a.dens_on) {
+  if (MODE & (kModeDensLds | kModeDensGlobal)) {
     const int eb = a.n_ebins > 1 ? energy_bin(s_edges, a.n_ebins, E) : 0;
     const int idx = (zb * a.n_ebins + eb) * 2 + s;
-    if (a.dens_lds) {
+    if (MODE & kModeDensLds) {
       atomicAdd(&s_dens[idx], 1u);
     } else {
       const int64_t g = I.dens_off + (int64_t)a.dens_slot * I.nz * a.n_ebins * 2 + idx;
       atomicAdd((unsigned long long*)&a.dens[g], 1ull);
     }
   }
-  if (a.cur_on) {
+  if (MODE & kModeCur) {
     const double vm = I.chan[layer_of(fl)][s].x * mu;
-    const long long val = (long long)rint(vm * 4294967296.0);
+    // round-half-even to an integer by adding 1.5*2^52 (|vm*2^32| < 2^51): the low
+    // mantissa bits then hold the integer, identical to rint()
+    const double sh = vm * 4294967296.0 + 0x1.8p52;
+    const long long val = __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
     atomicAdd(&s_cur[zb * 2 + s], (unsigned long long)val);
   }
 }
 
+template <int MODE>
 __device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
                            unsigned long long* s_cur) {
   __syncthreads();
-  if (a.dens_on && a.dens_lds) {
+  if (MODE & kModeDensLds) {
     const int n = I.nz * a.n_ebins * 2;
     unsigned long long* g =
         (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.dens_slot * n);
@@ -190,7 +217,7 @@ __device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens
       }
     }
   }
-  if (a.cur_on) {
+  if (MODE & kModeCur) {
     const int n = I.nz * 2;
     unsigned long long* g = (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.cur_slot * n);
     for (int b = threadIdx.x; b < n; b += blockDim.x) {
@@ -212,13 +239,81 @@ __device__ __forceinline__ void wave_add(unsigned long long* c, bool pred) {
   }
 }
 
-template <typename F>
+// Newborn secondaries wait in a wave-private LDS queue and are finished 64 at a time, so
+// the spawn draw, the newborn's half step, its deposit and its append run as full
+// waves instead of once per wave for a few lanes.
+constexpr int kQ = 128;
+struct ChildQueue {
+  double z[kQ];
+  uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ];
+};
+
+struct LaneCounts {
+  uint32_t dep, tr, ri, rs;
+};
+
+// Finish the top n entries of a wave's queue: spawn draw (direction, spin from the
+// layer's equilibrium polarisation, lineage), second half step, deposit and append.
+template <typename F, int MODE>
+__device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst& I, ChildQueue& Q,
+                                               int qn, int n, uint32_t* s_dens,
+                                               unsigned long long* s_cur, const uint32_t* s_edges,
+                                               int* s_app, int64_t base, int tail0, int cap,
+                                               LaneCounts& lc, bool& bad) {
+  constexpr bool DEBUG = (MODE & kModeDebug) != 0;
+  const int lane = __lane_id();
+  const bool act = lane < n;
+  const int idx = act ? qn - n + lane : 0;
+  double cz = Q.z[idx];
+  const uint32_t lo = Q.lo[idx], phi = Q.hi[idx], cE = Q.E[idx], pfl = Q.fl[idx];
+  if (act) {
+    const uint4 sw = philox10(lo, phi, (uint32_t)a.step, kTagSpawn, a.key0, a.key1);
+    const int l = layer_of(pfl);
+    double cmu = to_store<F>(dircos(sw.x));
+    const uint32_t cs = u01(sw.y) < I.lay[l].w ? 0u : 1u;
+    uint32_t lin = sw.z;
+    if (lin == 0u || lin == phi) {
+      lin = sw.w | 1u;
+      if (lin == phi) lin ^= 2u;
+    }
+    uint32_t cfl = cs | (pfl & ~kSpinMask);
+    HitCounts h{0, 0, 0};
+    half_push(I, cz, cmu, cfl, cE, lo, lin, (uint32_t)a.step, kTagHalf2, a.h, a.key0, a.key1, h, bad);
+    cz = to_store<F>(cz);
+    deposit<MODE>(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl);
+    lc.dep += 1;
+    lc.tr += h.tr;
+    lc.ri += h.ri;
+    lc.rs += h.rs;
+    const uint64_t m = __ballot(1);
+    int off = 0;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    if (lane == leader) off = atomicAdd(s_app, __popcll(m));
+    off = __shfl(off, leader);
+    const int pos = tail0 + off + __popcll(m & lanes_below());
+    if (pos < cap) {
+      const int64_t g = base + pos;
+      ((F*)a.z)[g] = (F)cz;
+      ((F*)a.mu)[g] = (F)cmu;
+      a.E[g] = cE;
+      a.uid[g] = (uint64_t)lo | ((uint64_t)lin << 32);
+      a.flags[g] = cfl;
+      if (DEBUG) a.ev[g] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
+    } else {
+      atomicOr(a.status, kStOverflow);
+    }
+  }
+}
+
+template <typename F, int MODE>
 __global__ void __launch_bounds__(256) k_step(StepArgs a) {
+  constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   extern __shared__ __align__(16) unsigned char dyn[];
   uint32_t* s_dens = (uint32_t*)dyn;
   unsigned long long* s_cur =
       (unsigned long long*)(dyn + (((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15));
   __shared__ DevInst s_inst;
+  __shared__ ChildQueue s_q[4];
   __shared__ unsigned long long s_cnt[kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
   __shared__ int s_slab, s_app, s_dead;
@@ -234,6 +329,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
   F* gz = (F*)a.z;
   F* gmu = (F*)a.mu;
   const uint32_t step = (uint32_t)a.step;
+  ChildQueue& Q = s_q[wave];
   int cur_inst = -1;
   bool bad = false;
 
@@ -244,7 +340,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
     if (slab >= a.n_slabs) break;
     const int inst = a.slab_inst[slab];
     if (inst != cur_inst) {
-      if (cur_inst >= 0) flush_bins(a, s_inst, s_dens, s_cur);
+      if (cur_inst >= 0) flush_bins<MODE>(a, s_inst, s_dens, s_cur);
       const uint4* src = (const uint4*)&a.inst[inst];
       uint4* dst = (uint4*)&s_inst;
       for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
@@ -265,9 +361,36 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
     const int64_t f0 = count_mod(cum[step], kk, S);
     const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
     const int total = tail0 + n_inj;
+    if (tid == 0 && n_inj) atomicAdd(&s_cnt[PIC_C_INJECTED], (unsigned long long)n_inj);
+    LaneCounts lc{0, 0, 0, 0};
+    int qn = 0;  // wave-uniform fill of this wave's child queue
 
+    // The slot a lane will handle in its next iteration is fetched one iteration ahead,
+    // unconditionally (a dead slot's fields are loaded too), so that no load waits on
+    // another and each wave keeps two particles' worth of loads in flight.
+    F nz = 0, nmu = 0;
+    uint32_t nE = 0, nfl = kDead;
+    uint64_t nu = 0, nev = 0;
+    auto fetch = [&](int t) {
+      if (t < tail0) {
+        const int64_t g = base + t;
+        nfl = a.flags[g];
+        nz = gz[g];
+        nmu = gmu[g];
+        nE = a.E[g];
+        nu = a.uid[g];
+        if (DEBUG) nev = a.ev[g];
+      } else {
+        nfl = kDead;
+      }
+    };
+    fetch(wave * 64 + lane);
     for (int tb = wave * 64; tb < total; tb += blockDim.x) {
       const int t = tb + lane;
+      const F rz = nz, rmu = nmu;
+      const uint32_t rE = nE, rfl = nfl;
+      const uint64_t ru = nu, rev = nev;
+      fetch(t + (int)blockDim.x);
       const bool have = t < total;
       const bool from_soa = have && t < tail0;
       const bool is_new = have && !from_soa;
@@ -276,15 +399,14 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
       uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
       uint64_t evp = 0;
       if (from_soa) {
-        fl = a.flags[gi];
+        fl = rfl;
         if (!(fl & kDead)) {
-          z = (double)gz[gi];
-          mu = (double)gmu[gi];
-          E = a.E[gi];
-          const uint64_t u = a.uid[gi];
-          lo = (uint32_t)u;
-          hi = (uint32_t)(u >> 32);
-          if (a.debug) evp = a.ev[gi];
+          z = (double)rz;
+          mu = (double)rmu;
+          E = rE;
+          lo = (uint32_t)ru;
+          hi = (uint32_t)(ru >> 32);
+          evp = rev;
         }
       } else if (is_new) {
         // Source term: one primary per root, Eq. (17)
@@ -308,12 +430,11 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
         hi = 0;
       }
       const bool alive0 = !(fl & kDead);
-      bool died = false, child = false;
+      bool died = false, spawn = false;
       uint32_t dirty = 0;  // 1: mu, 2: E, 4: flags
-      double cz = 0.0, cmu = 0.0;
-      uint32_t cE = 0, cfl = 0, clo = 0, chi = 0;
-      uint64_t cevp = 0;
-      HitCounts hc{0, 0, 0}, hcc{0, 0, 0};
+      double zmid = 0.0;
+      uint32_t E2 = 0, flmid = 0;
+      HitCounts hc{0, 0, 0};
       if (alive0) {
         const double mu_in = mu;
         const uint32_t fl_in = fl;
@@ -328,11 +449,18 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
         const double rate = Ek * I.chan[l][s].y + itel;
         const double x = a.dt * rate;
         const double u0 = u01(w.x);
-        // p = 1 - exp(-x) < x, so u0 >= x rejects without the transcendental
-        bool event = false;
-        if (u0 < x) event = u0 < -expm1(-x);
+        // event iff u0 < p = 1 - exp(-x), decided without the transcendental outside a
+        // sliver: x - x^2/2 < p < x, with a margin (about x^3/6) far above rounding
+        bool event;
+        if (u0 >= x) {
+          event = false;
+        } else if (x >= 0x1p-20 && u0 < x - 0.5 * x * x) {
+          event = true;
+        } else {
+          event = u0 < -expm1(-x);
+        }
         if (event) {
-          if (a.debug) evp += 1ull;
+          if (DEBUG) evp += 1ull;
           const bool elastic = itel > 0.0 && u01(w.y) < itel / rate;
           mu = to_store<F>(dircos(w.z));
           dirty |= 1u;
@@ -341,28 +469,15 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
           } else {
             atomicAdd(&s_cnt[PIC_C_EV_EE], 1ull);
             const uint32_t E1 = __umulhi(w.w, E);
-            const uint32_t E2 = E - E1;
+            E2 = E - E1;
             E = E1;
             dirty |= 2u;
             if (a.secondaries) {
               if (E2 >= a.e_min) {
-                const uint4 sw = philox10(lo, hi, step, kTagSpawn, a.key0, a.key1);
-                child = true;
-                cz = z;
-                cmu = to_store<F>(dircos(sw.x));
-                cE = E2;
-                const uint32_t cs = u01(sw.y) < I.lay[l].w ? 0u : 1u;
-                uint32_t gen = (fl >> kGenShift) & kGenMask;
-                gen = gen < 255u ? gen + 1u : 255u;
-                cfl = cs | ((uint32_t)l << kLayerShift) | (gen << kGenShift);
-                uint32_t lin = sw.z;
-                if (lin == 0u || lin == hi) {
-                  lin = sw.w | 1u;
-                  if (lin == hi) lin ^= 2u;
-                }
-                clo = lo;
-                chi = lin;
-                if (a.debug) evp += 1ull << 48;
+                spawn = true;
+                zmid = z;
+                flmid = fl;
+                if (DEBUG) evp += 1ull << 48;
                 atomicAdd(&s_cnt[PIC_C_SPAWNED], 1ull);
               } else {
                 atomicAdd(&s_cnt[PIC_C_SEC_ABSORBED], 1ull);
@@ -379,82 +494,89 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
         if (!died) {
           half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
           z = to_store<F>(z);
-          deposit(a, I, s_dens, s_cur, s_edges, z, mu, E, fl);
+          deposit<MODE>(a, I, s_dens, s_cur, s_edges, z, mu, E, fl);
+          lc.dep += 1;
         } else {
           z = to_store<F>(z);
           fl |= kDead;
         }
         if (mu != mu_in) dirty |= 1u;
         if (fl != fl_in) dirty |= 4u;
-        if (child) {
-          half_push(I, cz, cmu, cfl, cE, clo, chi, step, kTagHalf2, a.h, a.key0, a.key1, hcc, bad);
-          cz = to_store<F>(cz);
-          deposit(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl);
+        if (DEBUG) evp += ((uint64_t)hc.tr << 16) + ((uint64_t)(hc.ri + hc.rs) << 32);
+      }
+      lc.tr += hc.tr;
+      lc.ri += hc.ri;
+      lc.rs += hc.rs;
+
+      // ---- queue the newborns: (mid-step position, parent uid, energy, layer | gen)
+      const uint64_t mq = __ballot(spawn);
+      const uint64_t below = lanes_below();
+      if (mq) {
+        if (spawn) {
+          const int p = qn + __popcll(mq & below);
+          uint32_t gen = (flmid >> kGenShift) & kGenMask;
+          gen = gen < 255u ? gen + 1u : 255u;
+          Q.z[p] = zmid;
+          Q.lo[p] = lo;
+          Q.hi[p] = hi;
+          Q.E[p] = E2;
+          Q.fl[p] = (flmid & (kLayerMask << kLayerShift)) | (gen << kGenShift);
+        }
+        qn += __popcll(mq);
+      }
+      // ---- append the new primary (always, so that an absorbed one leaves its record)
+      const uint64_t ma = __ballot(is_new);
+      if (ma) {
+        int off = 0;
+        const int leader = __ffsll((unsigned long long)ma) - 1;
+        if (lane == leader) off = atomicAdd(&s_app, __popcll(ma));
+        off = __shfl(off, leader);
+        if (is_new) {
+          const int pos = tail0 + off + __popcll(ma & below);
+          if (pos < cap) {
+            const int64_t g = base + pos;
+            gz[g] = (F)z;
+            gmu[g] = (F)mu;
+            a.E[g] = E;
+            a.uid[g] = (uint64_t)lo | ((uint64_t)hi << 32);
+            a.flags[g] = fl;
+            if (DEBUG) a.ev[g] = evp;
+          } else {
+            atomicOr(a.status, kStOverflow);
+          }
         }
       }
-      if (hc.tr + hcc.tr) atomicAdd(&s_cnt[PIC_C_TRANSMIT], (unsigned long long)(hc.tr + hcc.tr));
-      if (hc.ri + hcc.ri) atomicAdd(&s_cnt[PIC_C_REFL_IF], (unsigned long long)(hc.ri + hcc.ri));
-      if (hc.rs + hcc.rs) atomicAdd(&s_cnt[PIC_C_REFL_SURF], (unsigned long long)(hc.rs + hcc.rs));
-      if (a.debug) {
-        // packed per-particle counts: events | transmissions << 16 | reflections << 32 |
-        // spawns << 48
-        evp += ((uint64_t)hc.tr << 16) + ((uint64_t)(hc.ri + hc.rs) << 32);
-        cevp = ((uint64_t)hcc.tr << 16) + ((uint64_t)(hcc.ri + hcc.rs) << 32);
-      }
-      wave_add(&s_cnt[PIC_C_INJECTED], is_new);
-      wave_add(&s_cnt[PIC_C_ALIVE], alive0 && !died);
-      wave_add(&s_cnt[PIC_C_ALIVE], child);
-
-      // ---- append the new primary (always, so that an absorbed one leaves its record)
-      // and the newborn behind the slab's tail: one LDS atomic per wave
-      const uint64_t ma = __ballot(is_new);
-      const uint64_t mb = __ballot(child);
-      const int na = __popcll(ma), nb = __popcll(mb);
-      int off = 0;
-      if (na + nb) {
-        const int leader = __ffsll((unsigned long long)(ma | mb)) - 1;
-        if (lane == leader) off = atomicAdd(&s_app, na + nb);
-        off = __shfl(off, leader);
-      }
-      const uint64_t below = lanes_below();
       if (from_soa && alive0) {
         gz[gi] = (F)z;
         if (dirty & 1u) gmu[gi] = (F)mu;
         if (dirty & 2u) a.E[gi] = E;
         if (dirty & 4u) a.flags[gi] = fl;
-        if (a.debug) a.ev[gi] = evp;
-      }
-      if (is_new) {
-        const int pos = tail0 + off + __popcll(ma & below);
-        if (pos < cap) {
-          const int64_t g = base + pos;
-          gz[g] = (F)z;
-          gmu[g] = (F)mu;
-          a.E[g] = E;
-          a.uid[g] = (uint64_t)lo | ((uint64_t)hi << 32);
-          a.flags[g] = fl;
-          if (a.debug) a.ev[g] = evp;
-        } else {
-          atomicOr(a.status, kStOverflow);
-        }
-      }
-      if (child) {
-        const int pos = tail0 + off + na + __popcll(mb & below);
-        if (pos < cap) {
-          const int64_t g = base + pos;
-          gz[g] = (F)cz;
-          gmu[g] = (F)cmu;
-          a.E[g] = cE;
-          a.uid[g] = (uint64_t)clo | ((uint64_t)chi << 32);
-          a.flags[g] = cfl;
-          if (a.debug) a.ev[g] = cevp;
-        } else {
-          atomicOr(a.status, kStOverflow);
-        }
+        if (DEBUG) a.ev[gi] = evp;
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
+      if (qn >= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        drain_children<F, MODE>(a, I, Q, qn, 64, s_dens, s_cur, s_edges, &s_app, base, tail0,
+                                cap, lc, bad);
+        qn -= 64;
+        __builtin_amdgcn_wave_barrier();
+      }
     }
+    if (qn > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      drain_children<F, MODE>(a, I, Q, qn, qn, s_dens, s_cur, s_edges, &s_app, base, tail0, cap,
+                              lc, bad);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lc.dep) atomicAdd(&s_cnt[PIC_C_ALIVE], (unsigned long long)lc.dep);
+    if (lc.tr) atomicAdd(&s_cnt[PIC_C_TRANSMIT], (unsigned long long)lc.tr);
+    if (lc.ri) atomicAdd(&s_cnt[PIC_C_REFL_IF], (unsigned long long)lc.ri);
+    if (lc.rs) atomicAdd(&s_cnt[PIC_C_REFL_SURF], (unsigned long long)lc.rs);
     __syncthreads();
     if (tid == 0) {
       int nt = tail0 + s_app;
@@ -463,7 +585,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
       a.slab_dead[slab] += s_dead;
     }
   }
-  if (cur_inst >= 0) flush_bins(a, s_inst, s_dens, s_cur);
+  if (cur_inst >= 0) flush_bins<MODE>(a, s_inst, s_dens, s_cur);
   if (bad) atomicOr(a.status, kStHits);
   __syncthreads();
   if (tid < kNC && s_cnt[tid])
@@ -545,13 +667,35 @@ __global__ void k_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, 
   }
 }
 
+template <typename F, int MODE>
+static void launch_mode(const StepArgs& a, int grid, int block, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_step<F, MODE>), dim3(grid), dim3(block), lds, s, a);
+}
+
+template <typename F>
+static hipError_t launch_prec(const StepArgs& a, int mode, int grid, int block, size_t lds,
+                              hipStream_t s) {
+  switch (mode) {
+#define PIC_MODE(m) \
+  case m:           \
+    launch_mode<F, m>(a, grid, block, lds, s); \
+    break;
+    PIC_MODE(0) PIC_MODE(1) PIC_MODE(2) PIC_MODE(3) PIC_MODE(4) PIC_MODE(5)
+    PIC_MODE(8) PIC_MODE(9) PIC_MODE(10) PIC_MODE(11) PIC_MODE(12) PIC_MODE(13)
+#undef PIC_MODE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
                        hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_step<double>, dim3(grid), dim3(block), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_step<float>, dim3(grid), dim3(block), lds, s, a);
-  return hipGetLastError();
+  const int mode = (a.debug ? kModeDebug : 0) |
+                   (a.dens_on ? (a.dens_lds ? kModeDensLds : kModeDensGlobal) : 0) |
+                   (a.cur_on ? kModeCur : 0);
+  return fp64 ? launch_prec<double>(a, mode, grid, block, lds, s)
+              : launch_prec<float>(a, mode, grid, block, lds, s);
 }
 
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s) {

@@ -131,6 +131,9 @@ class PicSim:
             n = self.problem.n_steps
         _abi.check(self.lib.pic_step(self.handle, int(n)))
 
+    def compact(self):
+        _abi.check(self.lib.pic_compact(self.handle))
+
     def reset(self):
         _abi.check(self.lib.pic_reset(self.handle))
 
