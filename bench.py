@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON dict of launch tuning")
     ap.add_argument("--slab", type=int, default=0)
+    ap.add_argument("--tune-steps", type=int, default=60,
+                    help="steps per autotuning trial (0: keep the default launch shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,6 +151,11 @@ def main():
     sim = PicSim(prob, device="cuda:0", slab_primaries=args.slab)
     if args.tuning:
         sim.set_tuning(**json.loads(args.tuning))
+    elif args.tune_steps > 0:
+        t0 = time.perf_counter()
+        tuned = sim.autotune(trial_steps=args.tune_steps)
+        print(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s: {tuned}",
+              file=sys.stderr, flush=True)
     for w in range(args.warmup):
         sim.reset()
         sim.step()

@@ -197,7 +197,7 @@ struct pic_ctx {
   int step = 0;
   bool sched_set = false;
   pic_tuning tune;
-  size_t lds_bytes = 0;
+  size_t lds_bytes = 0, max_lds = 0;
   int lds_dens_words = 0, lds_cur_words = 0, inst_bytes = 0;
   bool dens_lds = true;
   hipGraphExec_t gexec = nullptr;
@@ -216,6 +216,31 @@ void drop_graph(pic_ctx* c) {
   c->gexec = nullptr;
   c->graph = nullptr;
   c->g_start = c->g_n = -1;
+}
+
+// Dynamic LDS of one step launch (the layout k_step expects).
+size_t lds_for(const pic_ctx* c, int block, bool dens_step) {
+  const size_t dens = dens_step && c->dens_lds ? (size_t)c->lds_dens_words * 4 : 0;
+  const size_t cur_at = (dens + 15) & ~(size_t)15;
+  const size_t q_at = (cur_at + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
+  return q_at + (size_t)(block / 64) * kChildQueueBytes;
+}
+
+// Largest dynamic LDS a step launch may use: the device's per-workgroup limit minus the
+// kernel's static LDS, after raising the kernels' dynamic-LDS attribute to it.
+size_t device_lds_limit() {
+  static size_t cached = 0;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cached) return cached;
+  int dev = 0, per_block = 65536;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  const size_t stat = step_static_lds();
+  size_t lim = per_block > (int)stat ? (size_t)per_block - stat : 0;
+  if (lim > 65536 - stat && set_step_lds_limit(lim) != hipSuccess) lim = 65536 - stat;
+  cached = lim;
+  return cached;
 }
 
 StepArgs step_args(const pic_ctx* c, int n) {
@@ -291,7 +316,7 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
   grid = std::max(1, std::min(grid, n_slabs));
   for (int s = start; s < start + n; ++s) {
     StepArgs a = step_args(c, s);
-    const size_t lds = (((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15) + (size_t)a.lds_cur_words * 8;
+    const size_t lds = lds_for(c, c->tune.block, a.dens_on != 0);
     HIP_TRY(launch_step(a, fp64, grid, c->tune.block, lds, c->stream));
     if (c->tune.compact_every > 0 && !c->plan.debug && (s + 1) % c->tune.compact_every == 0 &&
         s + 1 < c->cfg.n_steps) {
@@ -415,17 +440,21 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
   c->tune.compact_every = 8;
   c->tune.compact_frac = 0.15f;
   c->tune.use_graph = 1;
-  // LDS histograms: the density slice and the current slice of the largest instance
+  // LDS per workgroup: the density slice and the current slice of the largest instance,
+  // plus one newborn queue per wave.  The density histogram goes to LDS when it fits
+  // next to the queues of a 256-thread block; otherwise density uses global atomics.
   int nz_max = 1;
   for (const auto& I : c->inst) nz_max = std::max(nz_max, I.nz);
   c->lds_cur_words = nz_max * 2;
   const int dens_words = nz_max * cfg->n_ebins * 2;
-  const size_t budget = 56 * 1024;
-  const size_t cur_bytes = (size_t)c->lds_cur_words * 8;
-  c->dens_lds = (size_t)dens_words * 4 + cur_bytes + 16 <= budget;
-  c->lds_dens_words = c->dens_lds ? dens_words : 0;
-  c->lds_bytes = (((size_t)c->lds_dens_words * 4 + 15) & ~(size_t)15) + cur_bytes;
-  if (cur_bytes > budget) {
+  c->lds_dens_words = dens_words;
+  c->dens_lds = true;
+  c->max_lds = device_lds_limit();
+  if (lds_for(c, 256, true) > c->max_lds) {
+    c->dens_lds = false;
+    c->lds_dens_words = 0;
+  }
+  if (lds_for(c, 64, false) > c->max_lds) {
     delete c;
     return fail(PIC_EINVAL, "too many depth bins for the LDS current histogram");
   }
@@ -533,9 +562,11 @@ pic_status pic_reset(pic_ctx* c) {
 pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (!c || !t) return fail(PIC_EINVAL, "null argument");
   const int b = t->block;
-  if (!(b == 64 || b == 128 || b == 256)) return fail(PIC_EINVAL, "block must be 64, 128 or 256");
+  if (!(b == 64 || b == 128 || b == 256 || b == 512)) return fail(PIC_EINVAL, "block must be 64, 128, 256 or 512");
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
+  if (lds_for(c, b, true) > c->max_lds)
+    return fail(PIC_EINVAL, "block too large for the LDS histograms of this configuration");
   c->tune = *t;
   drop_graph(c);
   return PIC_OK;
@@ -582,10 +613,106 @@ pic_status pic_backward(pic_ctx* c, const double*, const double*, double*, int32
   return fail(PIC_ESTATE, "adjoint not available in this build");
 }
 
-pic_status pic_autotune(pic_ctx* c, int32_t, pic_tuning* best) {
+// Signature of a configuration for the tuning cache: every byte of the config struct and
+// of the instance tables, plus the device.
+static uint64_t config_signature(const pic_ctx* c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  pic_config cfg = c->cfg;
+  cfg.inst = nullptr;
+  mix(&cfg, sizeof(cfg));
+  mix(c->inst.data(), c->inst.size() * sizeof(pic_instance));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  mix(&dev, sizeof(dev));
+  return h;
+}
+
+static std::mutex g_tune_mu;
+static std::map<uint64_t, pic_tuning> g_tune_cache;
+
+// Time `steps` steps from a cleared state with the given tuning (ms on the stream).
+static pic_status time_trial(pic_ctx* c, const pic_tuning& t, int steps, float* ms) {
+  pic_status st = pic_set_tuning(c, &t);
+  if (st != PIC_OK) return st;
+  st = clear_state(c);
+  if (st != PIC_OK) return st;
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  HIP_TRY(hipEventRecord(a, c->stream));
+  st = enqueue_steps(c, 0, steps);
+  HIP_TRY(hipEventRecord(b, c->stream));
+  HIP_TRY(hipEventSynchronize(b));
+  HIP_TRY(hipEventElapsedTime(ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   if (!c) return fail(PIC_EINVAL, "null context");
-  if (best) *best = c->tune;
-  return PIC_OK;
+  if (!c->sched_set) return fail(PIC_ESTATE, "pic_inject must precede pic_autotune");
+  const int steps = std::max(1, std::min<int>(trial_steps, c->cfg.n_steps));
+  const uint64_t key = config_signature(c);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      pic_status st = pic_set_tuning(c, &it->second);
+      if (st != PIC_OK) return st;
+      if (best) *best = it->second;
+      return clear_state(c);
+    }
+  }
+  pic_tuning cur = c->tune;
+  cur.use_graph = 0;
+  float best_ms = 1e30f;
+  pic_tuning win = cur;
+  // stage 1: workgroup size and persistent grid
+  for (int block : {128, 256, 512}) {
+    if (lds_for(c, block, true) > c->max_lds) continue;
+    for (int grid : {256, 512, 1024, 2048}) {
+      pic_tuning t = cur;
+      t.block = block;
+      t.grid = grid;
+      float ms = 0;
+      pic_status st = time_trial(c, t, steps, &ms);
+      if (st != PIC_OK) return st;
+      if (ms < best_ms) {
+        best_ms = ms;
+        win = t;
+      }
+    }
+  }
+  // stage 2: compaction cadence and threshold
+  for (int every : {4, 8, 16, 0}) {
+    for (float frac : {0.1f, 0.25f}) {
+      if (every == 0 && frac > 0.1f) continue;
+      pic_tuning t = win;
+      t.compact_every = every;
+      t.compact_frac = frac;
+      float ms = 0;
+      pic_status st = time_trial(c, t, steps, &ms);
+      if (st != PIC_OK) return st;
+      if (ms < best_ms) {
+        best_ms = ms;
+        win = t;
+      }
+    }
+  }
+  win.use_graph = 1;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = win;
+  }
+  pic_status st = pic_set_tuning(c, &win);
+  if (st != PIC_OK) return st;
+  if (best) *best = win;
+  return clear_state(c);
 }
 
 void pic_destroy(pic_ctx* c) {

@@ -101,10 +101,15 @@ struct CompactArgs {
   float frac;
 };
 
+// bytes of one wave's newborn queue in dynamic LDS (see pic_kernels.hip)
+constexpr size_t kChildQueueBytes = 128 * (8 + 4 * 4);
+
 // launchers (pic_kernels.hip)
 hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
                        hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s);
+size_t step_static_lds();
+hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
                           double* dout, double* cout, hipStream_t s);

@@ -243,7 +243,7 @@ __device__ __forceinline__ void wave_add(unsigned long long* c, bool pred) {
 // the spawn draw, the newborn's half step, its deposit and its append run as full
 // waves instead of once per wave for a few lanes.
 constexpr int kQ = 128;
-struct ChildQueue {
+struct ChildQueue {  // kChildQueueBytes
   double z[kQ];
   uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ];
 };
@@ -306,14 +306,15 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
 }
 
 template <typename F, int MODE>
-__global__ void __launch_bounds__(256) k_step(StepArgs a) {
+__global__ void __launch_bounds__(512) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
+  // dynamic LDS: [density histogram | current histogram | one child queue per wave]
   extern __shared__ __align__(16) unsigned char dyn[];
   uint32_t* s_dens = (uint32_t*)dyn;
-  unsigned long long* s_cur =
-      (unsigned long long*)(dyn + (((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15));
+  const size_t cur_at = ((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15;
+  unsigned long long* s_cur = (unsigned long long*)(dyn + cur_at);
+  ChildQueue* s_q = (ChildQueue*)(dyn + ((cur_at + (size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15));
   __shared__ DevInst s_inst;
-  __shared__ ChildQueue s_q[4];
   __shared__ unsigned long long s_cnt[kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
   __shared__ int s_slab, s_app, s_dead;
@@ -330,6 +331,7 @@ __global__ void __launch_bounds__(256) k_step(StepArgs a) {
   F* gmu = (F*)a.mu;
   const uint32_t step = (uint32_t)a.step;
   ChildQueue& Q = s_q[wave];
+  static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   int cur_inst = -1;
   bool bad = false;
 
@@ -687,6 +689,30 @@ static hipError_t launch_prec(const StepArgs& a, int mode, int grid, int block, 
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+size_t step_static_lds() {
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_step<double, kModeDensLds | kModeCur>)) != hipSuccess)
+    return 8192;
+  return fa.sharedSizeBytes;
+}
+
+template <typename F, int MODE>
+static hipError_t raise_lds(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<F, MODE>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t set_step_lds_limit(size_t bytes) {
+  hipError_t e = hipSuccess;
+#define PIC_RAISE(m)                                         \
+  if (e == hipSuccess) e = raise_lds<float, m>(bytes);       \
+  if (e == hipSuccess) e = raise_lds<double, m>(bytes);
+  PIC_RAISE(0) PIC_RAISE(1) PIC_RAISE(2) PIC_RAISE(3) PIC_RAISE(4) PIC_RAISE(5)
+  PIC_RAISE(8) PIC_RAISE(9) PIC_RAISE(10) PIC_RAISE(11) PIC_RAISE(12) PIC_RAISE(13)
+#undef PIC_RAISE
+  return e;
 }
 
 hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,

@@ -160,3 +160,23 @@ def test_reset_replays_identically(torch_gpu):
     b = sim.int_bins()
     sim.close()
     assert all(np.array_equal(x, y) for x, y in zip(a[0] + a[1], b[0] + b[1]))
+
+
+def test_autotune_keeps_results(torch_gpu, oracle_mod):
+    from paper_1807_04733_amd import PicSim
+    prob = W.config2(n_instances=5, n_steps=60, prim_lo=300, prim_hi=4000)
+    ref = oracle_mod.run(prob)
+    sim = PicSim(prob, slab_primaries=600)
+    tuned = sim.autotune(trial_steps=20)
+    _say(f"[parity] autotuned {tuned}")
+    assert tuned["block"] in (128, 256, 512) and tuned["grid"] > 0
+    again = sim.autotune(trial_steps=20)          # served from the cache
+    assert again == tuned
+    sim.step()
+    dens, cur = sim.int_bins()
+    cnt = sim.counters()
+    sim.close()
+    for i in range(len(prob.instances)):
+        assert np.array_equal(dens[i], ref.dens[i])
+        assert np.array_equal(cur[i], ref.cur[i])
+    assert np.array_equal(cnt, ref.counters)
