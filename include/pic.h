@@ -119,6 +119,10 @@ typedef struct {
   int32_t  dens_stride, cur_stride;         /* deposit every k-th step (slot n/k) */
   int32_t  slab_primaries;                  /* primaries per slab; 0 = 4096 */
   double   capacity_factor;                 /* slots per primary; 0 = floor(E0max/Emin)+2 */
+  int32_t  adjoint;                         /* workspace for pic_backward: 0 none, 1 causal
+                                               (K <= 16), 2 whole-tree, 3 both.  Needs equal
+                                               table shapes in all instances and
+                                               n_steps <= 32767 */
 } pic_config;
 
 /* Launch tuning.  Results never depend on it. */
@@ -174,9 +178,13 @@ pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
  * to ln tau0 per channel and every transmission-table entry, written to grad_out
  * (device, [n_channels + n_ttables*t_entries], summed over instances).  Replays the run
  * from step 0 with the same random streams (the particle state is rebuilt; bins are
- * untouched).  estimator 0: causal score carried by each carrier (needs K <= 16);
- * 1: whole-tree return.  g_dens / g_cur: device arrays laid out like pic_deposit's
- * outputs (either may be NULL). */
+ * untouched).  estimator 0: causal score carried by each carrier (needs K <= 16 and
+ * adjoint 1 or 3); 1: whole-tree return, two replays (adjoint 2 or 3).  g_dens / g_cur:
+ * device arrays laid out like pic_deposit's outputs (either may be NULL).  Parameter
+ * order: ln tau0 of channels 0..n_channels-1, then T[t][e] row-major.  The result is an
+ * unbiased Monte-Carlo estimate on the same random streams as the forward run.  The
+ * replay does not compact, so the workspace must hold every carrier ever created
+ * (capacity_factor).  Synchronizes. */
 pic_status pic_backward(pic_ctx* ctx, const double* g_dens, const double* g_cur,
                         double* grad_out, int32_t estimator);
 

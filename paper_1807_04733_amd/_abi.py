@@ -57,7 +57,7 @@ class PicConfig(C.Structure):
         ("e_min_fx", C.c_uint32), ("flags", C.c_uint32), ("n_ebins", C.c_int32),
         ("e_edges", C.c_uint32 * MAX_EBINS), ("dens_stride", C.c_int32),
         ("cur_stride", C.c_int32), ("slab_primaries", C.c_int32),
-        ("capacity_factor", C.c_double),
+        ("capacity_factor", C.c_double), ("adjoint", C.c_int32),
     ]
 
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpic.so")
-SOURCES = ["pic_kernels.hip", "pic_api.hip"]
+SOURCES = ["pic_kernels.hip", "pic_adjoint.hip", "pic_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")

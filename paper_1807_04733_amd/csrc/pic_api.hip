@@ -49,7 +49,9 @@ struct Plan {
   int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
   int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
   int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
-  int64_t off_grad, off_score;
+  int64_t off_grad = -1, off_S = -1, off_r = -1, off_R = -1;
+  int K = 0;
+  int64_t n_roots = 0;
   int64_t bytes = 0;
 };
 
@@ -108,6 +110,18 @@ pic_status validate(const pic_config* c) {
     if (I.root_offset + (uint64_t)I.n_primaries > 0x100000000ull)
       return fail(PIC_EINVAL, w + "root ids must fit in 32 bits");
     roots_end = std::max(roots_end, I.root_offset + (uint64_t)I.n_primaries);
+  }
+  if (c->adjoint < 0 || c->adjoint > 3) return fail(PIC_EINVAL, "adjoint must be 0..3");
+  if (c->adjoint) {
+    const pic_instance& I0 = c->inst[0];
+    for (int i = 1; i < c->n_instances; ++i)
+      if (c->inst[i].n_channels != I0.n_channels || c->inst[i].n_ttables != I0.n_ttables ||
+          c->inst[i].t_entries != I0.t_entries)
+        return fail(PIC_EINVAL, "adjoint needs the same table shapes in every instance");
+    if (c->n_steps > 32767) return fail(PIC_EINVAL, "adjoint supports at most 32767 steps");
+    const int K = I0.n_channels + I0.n_ttables * I0.t_entries;
+    if ((c->adjoint & 1) && K > kMaxCausalK)
+      return fail(PIC_EINVAL, "causal adjoint supports at most 16 parameters");
   }
   return PIC_OK;
 }
@@ -179,6 +193,18 @@ Plan make_plan(const pic_config* c) {
   p.off_counters = take((int64_t)c->n_steps * kNC * 8);
   p.off_queue = take((int64_t)c->n_steps * 4 * 2);
   p.off_status = take(64);
+  if (c->adjoint) {
+    const pic_instance& I0 = c->inst[0];
+    p.K = I0.n_channels + I0.n_ttables * I0.t_entries;
+    for (int i = 0; i < c->n_instances; ++i)
+      p.n_roots = std::max<int64_t>(p.n_roots, (int64_t)c->inst[i].root_offset + c->inst[i].n_primaries);
+    p.off_grad = take((int64_t)p.K * 8);
+    if (c->adjoint & 1) p.off_S = take(C * p.K * 8);
+    if (c->adjoint & 2) {
+      p.off_r = take(C * 8);
+      p.off_R = take(std::max<int64_t>(p.n_roots, 1) * 8);
+    }
+  }
   p.bytes = o;
   return p;
 }
@@ -369,6 +395,8 @@ pic_status upload_tables(pic_ctx* c) {
     for (int k = 0; k < I.n_layers - 1; ++k)
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s) D.tt[k][d][s] = (uint8_t)I.tt_of[k][d][s];
+    for (int l = 0; l < I.n_layers; ++l)
+      for (int s = 0; s < 2; ++s) D.chi[l][s] = (uint8_t)I.ch_of[l][s];
     for (int t = 0; t < I.n_ttables; ++t)
       for (int e = 0; e < I.t_entries; ++e) D.T[t * I.t_entries + e] = I.T[t][e];
     max_tab = std::max(max_tab, I.n_ttables * I.t_entries);
@@ -608,9 +636,76 @@ pic_status pic_layout_of(const pic_ctx* c, pic_layout* o) {
   return PIC_OK;
 }
 
-pic_status pic_backward(pic_ctx* c, const double*, const double*, double*, int32_t) {
-  if (!c) return fail(PIC_EINVAL, "null context");
-  return fail(PIC_ESTATE, "adjoint not available in this build");
+// Clear the particle population only (the forward bins and counters stay).
+static pic_status clear_particles(pic_ctx* c) {
+  const Plan& p = c->plan;
+  const int64_t NS = (int64_t)p.slab_inst.size();
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_slab_tail), NS, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_slab_dead), NS, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_queue), (int64_t)c->cfg.n_steps * 2, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_status), 16, 0, c->stream));
+  return PIC_OK;
+}
+
+static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double* g_cur) {
+  const Plan& p = c->plan;
+  const bool fp64 = p.state_bytes == 8;
+  const int n_slabs = (int)p.slab_inst.size();
+  int grid = c->tune.grid > 0 ? c->tune.grid : 512;
+  grid = std::max(1, std::min(grid, n_slabs));
+  const int block = std::min(c->tune.block, 256);
+  pic_status st = clear_particles(c);
+  if (st != PIC_OK) return st;
+  AdjArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.S = c->at<double>(p.off_S);
+  A.r = c->at<double>(p.off_r);
+  A.R = c->at<double>(p.off_R);
+  A.g_dens = g_dens;
+  A.g_cur = g_cur;
+  A.grad = c->at<double>(p.off_grad);
+  A.K = p.K;
+  A.n_ch = c->inst[0].n_channels;
+  for (int n = 0; n < c->cfg.n_steps; ++n) {
+    A.s = step_args(c, n);
+    HIP_TRY(launch_adjoint(A, fp64, adj, grid, block, c->stream));
+  }
+  A.s = step_args(c, c->cfg.n_steps - 1);
+  HIP_TRY(launch_adjoint_final(A, fp64, adj, (uint32_t)c->cfg.n_steps, c->stream));
+  return PIC_OK;
+}
+
+pic_status pic_backward(pic_ctx* c, const double* g_dens, const double* g_cur, double* grad_out,
+                        int32_t estimator) {
+  if (!c || !grad_out) return fail(PIC_EINVAL, "null argument");
+  if (!c->sched_set) return fail(PIC_ESTATE, "pic_inject must precede pic_backward");
+  const Plan& p = c->plan;
+  if (estimator == 0 && p.off_S < 0)
+    return fail(PIC_ESTATE, "causal adjoint needs a context created with adjoint 1 or 3");
+  if (estimator == 1 && p.off_R < 0)
+    return fail(PIC_ESTATE, "whole-tree adjoint needs a context created with adjoint 2 or 3");
+  if (estimator != 0 && estimator != 1) return fail(PIC_EINVAL, "estimator must be 0 or 1");
+  drop_graph(c);
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_grad), (int64_t)p.K * 2, 0, c->stream));
+  pic_status st;
+  if (estimator == 0) {
+    st = replay(c, 1, g_dens, g_cur);
+  } else {
+    HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_R), std::max<int64_t>(p.n_roots, 1) * 2, 0, c->stream));
+    st = replay(c, 2, g_dens, g_cur);
+    if (st == PIC_OK) st = replay(c, 3, g_dens, g_cur);
+  }
+  if (st != PIC_OK) return st;
+  HIP_TRY(hipMemcpyAsync(grad_out, c->at<void>(p.off_grad), (size_t)p.K * 8,
+                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->step = c->cfg.n_steps;
+  uint32_t status = 0;
+  HIP_TRY(hipMemcpy(&status, c->at<void>(p.off_status), 4, hipMemcpyDeviceToHost));
+  if (status & kStOverflow)
+    return fail(PIC_ECAPACITY, "particle slots exhausted in the adjoint replay: raise capacity_factor");
+  if (status & kStHits) return fail(PIC_ESTATE, "more than 8 boundary hits in one half step");
+  return PIC_OK;
 }
 
 // Signature of a configuration for the tuning cache: every byte of the config struct and

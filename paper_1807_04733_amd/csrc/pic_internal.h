@@ -10,6 +10,8 @@ namespace pic {
 constexpr int kMaxL = PIC_MAX_LAYERS;
 constexpr int kMaxT = PIC_MAX_TTABLES * PIC_MAX_TENTRIES;
 constexpr int kMaxHits = 8;
+constexpr int kMaxK = PIC_MAX_CHANNELS + PIC_MAX_TTABLES * PIC_MAX_TENTRIES;  // adjoint parameters
+constexpr int kMaxCausalK = 16;
 constexpr int kNC = PIC_NCOUNTERS;
 
 // Random-number purposes (fourth counter word).  One fixed slot per purpose so that a
@@ -46,6 +48,7 @@ struct alignas(32) DevInst {
   int64_t dens_off, cur_off;   // element offsets of this instance in the global bins
   int32_t slab0, pad1;
   uint8_t tt[kMaxL - 1][2][2]; // transmission table per (interface, direction, spin)
+  uint8_t chi[kMaxL][2];       // channel index per (layer, spin) (adjoint parameter slot)
   uint8_t pad2[4];
   double T[kMaxT];             // [table][entry]; only the first n_ttables*t_entries used
 };
@@ -87,6 +90,17 @@ struct StepArgs {
   int32_t inst_bytes;          // bytes of DevInst copied into LDS
 };
 
+struct AdjArgs {
+  StepArgs s;                  // the dynamics, exactly as in the forward step
+  double* S;                   // causal score rows [capacity][K]
+  double* r;                   // per-carrier partial return [capacity]
+  double* R;                   // per-tree return [n_roots]
+  const double* g_dens;        // dL/d(density), laid out like the bins, or null
+  const double* g_cur;         // dL/d(current) per nm/fs, or null
+  double* grad;                // [K] accumulator
+  int32_t K, n_ch;
+};
+
 struct CompactArgs {
   void* z;
   void* mu;
@@ -108,6 +122,10 @@ constexpr size_t kChildQueueBytes = 128 * (8 + 4 * 4);
 hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
                        hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& A, bool fp64, int adj, int grid, int block,
+                          hipStream_t s);
+hipError_t launch_adjoint_final(const AdjArgs& A, bool fp64, int adj, uint32_t n_steps,
+                                hipStream_t s);
 size_t step_static_lds();
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

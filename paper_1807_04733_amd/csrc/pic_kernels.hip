@@ -17,157 +17,12 @@
 // Histograms are privatised per workgroup in LDS and merged into the int64 bins with
 // global atomics only for non-zero entries.  All decisions use binary64 arithmetic in
 // the order written here; the file is built with -ffp-contract=off.
-#include "pic_internal.h"
+#include "pic_device.h"
 
 #pragma clang fp contract(off)
 
 namespace pic {
 
-// ------------------------------------------------------------------------- Philox4x32-10
-// Salmon et al. (SC'11).  Two 32x32->64 products per round (v_mad_u64_u32); the key is
-// wave-uniform, so its Weyl schedule stays in scalar registers.
-// Three-input XOR with the round key in a scalar register: gfx950's three-operand
-// bitwise op with truth table 0x96 (odd parity), one VALU op instead of two.
-__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
-  uint32_t r;
-  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
-  return r;
-}
-// Scalar add for the Weyl key schedule; volatile so that the 20 round keys are
-// recomputed per call on the scalar unit instead of being kept live in SGPRs.
-__device__ __forceinline__ uint32_t key_step(uint32_t k, uint32_t w) {
-  uint32_t r;
-  asm volatile("s_add_u32 %0, %1, %2" : "=s"(r) : "s"(k), "s"(w) : "scc");
-  return r;
-}
-
-__device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                          uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t m0 = (uint64_t)x0 * 0xD2511F53ull;
-    const uint64_t m1 = (uint64_t)x2 * 0xCD9E8D57ull;
-    const uint32_t y0 = xor3_key((uint32_t)(m1 >> 32), x1, k0);
-    const uint32_t y2 = xor3_key((uint32_t)(m0 >> 32), x3, k1);
-    x1 = (uint32_t)m1;
-    x3 = (uint32_t)m0;
-    x0 = y0;
-    x2 = y2;
-    if (r < 9) {
-      k0 = key_step(k0, 0x9E3779B9u);
-      k1 = key_step(k1, 0xBB67AE85u);
-    }
-  }
-  return make_uint4(x0, x1, x2, x3);
-}
-
-// uniform on (0,1) and direction cosine on (-1,1): exact in binary64
-__device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
-__device__ __forceinline__ double dircos(uint32_t w) { return ((double)w + 0.5) * 0x1p-31 - 1.0; }
-
-template <typename F>
-__device__ __forceinline__ double to_store(double x) { return (double)(F)x; }
-
-__device__ __forceinline__ int layer_of(uint32_t fl) { return (int)((fl >> kLayerShift) & kLayerMask); }
-
-__device__ __forceinline__ double trans_prob(const DevInst& I, int t, uint32_t E) {
-  const int TE = I.t_entries;
-  const double* tab = I.T + t * TE;
-  if (TE == 1) return tab[0];
-  const double x = ((double)E * 0x1p-30) * I.T_scale;
-  const int k = (int)floor(x);
-  if (k >= TE - 1) return tab[TE - 1];
-  const double f = x - (double)k;
-  return tab[k] + (tab[k + 1] - tab[k]) * f;
-}
-
-struct HitCounts {
-  uint32_t tr, ri, rs;
-};
-
-// Transport over half a step.  The common case (no boundary reached) costs one LDS read
-// of the layer and one of the channel; boundary handling is a rarely taken loop.
-__device__ __forceinline__ void half_push(const DevInst& I, double& z, double& mu, uint32_t& fl,
-                                          uint32_t E, uint32_t lo, uint32_t hi, uint32_t step,
-                                          uint32_t tag, double h, uint32_t k0, uint32_t k1,
-                                          HitCounts& hc, bool& bad) {
-  int l = layer_of(fl);
-  const int s = (int)(fl & kSpinMask);
-  const double v = I.chan[l][s].x;
-  double ze = z + (v * mu) * h;
-  double zlo = I.lay[l].x, zhi = I.lay[l].y;
-  if (ze > zhi || ze < zlo) {
-    uint32_t draws = 0;
-    for (int hit = 0;; ++hit) {
-      const bool up = ze > zhi;
-      if (!up && !(ze < zlo)) break;
-      if (hit == kMaxHits) {
-        bad = true;
-        ze = up ? zhi : zlo;
-        break;
-      }
-      const double b = up ? zhi : zlo;
-      const bool outer = up ? (l == I.n_layers - 1) : (l == 0);
-      if (outer) {
-        ze = b - (ze - b);
-        mu = -mu;
-        ++hc.rs;
-        continue;
-      }
-      const int iface = up ? l : l - 1;
-      const int nl = up ? l + 1 : l - 1;
-      const double T = trans_prob(I, I.tt[iface][up ? 0 : 1][s], E);
-      bool go;
-      if (T >= 1.0) {
-        go = true;           // a draw in (0,1) is always below T
-      } else if (T <= 0.0) {
-        go = false;
-      } else {
-        const uint4 w = philox10(lo, hi, step, tag + draws, k0, k1);
-        go = u01(w.x) < T;
-      }
-      ++draws;
-      if (go) {
-        // speed ratio new/old layer, divided once on the host (same IEEE quotient)
-        const double r = I.ratio[l][s][up ? 0 : 1];
-        ze = b + (ze - b) * r;
-        l = nl;
-        zlo = I.lay[l].x;
-        zhi = I.lay[l].y;
-        ++hc.tr;
-      } else {
-        ze = b - (ze - b);
-        mu = -mu;
-        ++hc.ri;
-      }
-    }
-    fl = (fl & ~(kLayerMask << kLayerShift)) | ((uint32_t)l << kLayerShift);
-  }
-  z = ze;
-}
-
-__device__ __forceinline__ int energy_bin(const uint32_t* edges, int n, uint32_t E) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (edges[mid] <= E) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int64_t count_mod(int64_t x, int64_t k, int64_t S) {
-  // number of j in [0, x) with j % S == k
-  return x > k ? (x - 1 - k) / S + 1 : 0;
-}
-
-__device__ __forceinline__ uint64_t lanes_below() {
-  const int lane = __lane_id();
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Deposit one carrier at the end of the step: density per (depth, energy, spin) and the
-// fixed-point current v*cos(theta) per (depth, spin).
 // Compile-time launch modes of the step kernel.
 constexpr int kModeDebug = 1;       // keep per-particle event counts
 constexpr int kModeDensLds = 2;     // this step deposits density into LDS

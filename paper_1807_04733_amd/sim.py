@@ -14,7 +14,7 @@ from . import _abi
 
 
 def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
-                capacity_factor: float = 0.0):
+                capacity_factor: float = 0.0, adjoint: int = 0):
     """Translate a workloads.Problem into the C structs (returns config and a keep-alive)."""
     insts = (_abi.PicInstance * len(problem.instances))()
     for i, it in enumerate(problem.instances):
@@ -76,6 +76,7 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
     cfg.cur_stride = int(problem.cur_stride)
     cfg.slab_primaries = int(slab_primaries)
     cfg.capacity_factor = float(capacity_factor)
+    cfg.adjoint = int(adjoint)
     return cfg, insts
 
 
@@ -91,7 +92,7 @@ class PicSim:
 
     def __init__(self, problem, *, device="cuda", debug: bool = False,
                  slab_primaries: int = 0, capacity_factor: float = 0.0, stream=None,
-                 tuning: Optional[dict] = None):
+                 tuning: Optional[dict] = None, adjoint: int = 0):
         import torch
 
         self.problem = problem
@@ -99,7 +100,7 @@ class PicSim:
         self.device = torch.device(device)
         self._cfg, self._keep = make_config(problem, debug=debug,
                                             slab_primaries=slab_primaries,
-                                            capacity_factor=capacity_factor)
+                                            capacity_factor=capacity_factor, adjoint=adjoint)
         n = C.c_int64()
         _abi.check(self.lib.pic_workspace_size(C.byref(self._cfg), C.byref(n)))
         self.ws_bytes = n.value
@@ -152,6 +153,40 @@ class PicSim:
         t = _abi.PicTuning()
         _abi.check(self.lib.pic_autotune(self.handle, int(trial_steps), C.byref(t)))
         return {k: getattr(t, k) for k, _ in t._fields_}
+
+    @property
+    def n_params(self) -> int:
+        it = self.problem.instances[0]
+        return it.n_channels + it.n_ttables * it.t_entries
+
+    def backward(self, g_dens=None, g_cur=None, estimator: int = 0) -> np.ndarray:
+        """Likelihood-ratio gradient of sum(g_dens*dens) + sum(g_cur*cur) with respect to
+        (ln tau0 per channel, T table nodes).  g_* are per-instance arrays shaped like
+        the bins (or one flat array / device tensor each), or None."""
+        import torch
+
+        def flat(g):
+            if g is None:
+                return None
+            if isinstance(g, (list, tuple)):
+                g = torch.cat([torch.as_tensor(x, dtype=torch.float64).reshape(-1).to(self.device)
+                               for x in g])
+            return torch.as_tensor(g, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+
+        with torch.cuda.stream(self.stream):
+            gd = flat(g_dens)
+            gc = flat(g_cur)
+            if gd is not None and gd.numel() != self.layout.dens_len:
+                raise ValueError("g_dens does not match the density bins")
+            if gc is not None and gc.numel() != self.layout.cur_len:
+                raise ValueError("g_cur does not match the current bins")
+            grad = torch.zeros(self.n_params, dtype=torch.float64, device=self.device)
+            torch.cuda.current_stream(self.device).synchronize()
+            _abi.check(self.lib.pic_backward(
+                self.handle, C.c_void_p(gd.data_ptr() if gd is not None else 0),
+                C.c_void_p(gc.data_ptr() if gc is not None else 0),
+                C.c_void_p(grad.data_ptr()), int(estimator)))
+        return grad.cpu().numpy()
 
     def counters(self) -> np.ndarray:
         out = np.zeros((self.problem.n_steps, _abi.NCOUNTERS), np.int64)
