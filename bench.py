@@ -112,6 +112,160 @@ def cpu_baseline(prob, roots: int):
                        f"{ps} particle-steps, {dt:.1f} s wall)")
 
 
+def adjoint_leg(n_primaries: int, tune_steps: int):
+    """Plain single-instance forward and its causal adjoint on the Fe(15)/Au(80) bilayer
+    (E0 ~ U(0.5, 2) eV, 400 x 1 fs): loss = L2 distance of the spin current at z = 80 nm
+    to a target curve; the adjoint returns 8 gradients (4 tau0, 4 T)."""
+    import torch
+    from paper_1807_04733_amd import PicSim
+
+    prob = W.config3(n_primaries=n_primaries)
+    # the replay keeps every carrier ever created (7.3 per primary on average at this
+    # workload, at most 20 per tree): 10 slots per primary over 8192-primary slabs
+    sim = PicSim(prob, device="cuda:0", adjoint=1, slab_primaries=8192, capacity_factor=10)
+    if tune_steps > 0:
+        sim.autotune(trial_steps=tune_steps)
+    sim.step()
+    sim.counters()
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step()
+    cnt = sim.counters()
+    t_fwd = time.perf_counter() - t0
+    d, c = sim.deposit()
+    js = c[0][:, 80, 0] - c[0][:, 80, 1]
+    target = 0.9 * js
+    g_cur = torch.zeros_like(c[0])
+    g_cur[:, 80, 0] = 2 * (js - target)
+    g_cur[:, 80, 1] = -2 * (js - target)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad = sim.backward(None, g_cur, 0)
+    t_bwd = time.perf_counter() - t0
+    ps = particle_steps(cnt)
+    sim.close()
+    del d, c, g_cur
+    torch.cuda.empty_cache()
+    return dict(workload=f"fe15_au80_bilayer: {n_primaries:.0e} primaries U(0.5,2) eV, 400 x 1 fs, "
+                         "FP32 state, L2 loss on the spin current at z = 80 nm, 8 parameters",
+                particle_steps=ps, forward_s=round(t_fwd, 4), adjoint_s=round(t_bwd, 4),
+                adjoint_over_forward=round(t_bwd / t_fwd, 3),
+                fwd_plus_adjoint_particle_steps_per_s=2 * ps / (t_fwd + t_bwd),
+                estimator="causal score rows, lazy non-event flush",
+                grad=[float(x) for x in grad])
+
+
+def sequential_leg(prob, batched_s: float):
+    """The same stacks run one after another, one context and one graph each."""
+    import torch
+    from dataclasses import replace as dc_replace
+    from paper_1807_04733_amd import PicSim
+
+    total = 0.0
+    ps = 0
+    for inst in prob.instances:
+        one = dc_replace(prob, instances=[inst])
+        sim = PicSim(one, device="cuda:0")
+        sim.step()
+        sim.counters()
+        sim.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step()
+        cnt = sim.counters()
+        total += time.perf_counter() - t0
+        ps += particle_steps(cnt)
+        sim.close()
+    torch.cuda.empty_cache()
+    return dict(instances=len(prob.instances), sequential_s=round(total, 4),
+                batched_s=round(batched_s, 4), batched_speedup=round(total / batched_s, 3),
+                particle_steps=ps)
+
+
+def summarize_trace(path: str):
+    """Per-kernel statistics of a rocprofv3 --kernel-trace CSV (ms)."""
+    import csv
+    import collections
+
+    rows = list(csv.DictReader(open(path)))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        agg[r["Kernel_Name"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+    tot = sum(sum(v) for v in agg.values())
+    print(f"{'kernel':64s} {'calls':>6s} {'total_ms':>10s} {'mean_ms':>9s} {'share':>6s}")
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        print(f"{k[:64]:64s} {len(v):6d} {sum(v):10.3f} {sum(v) / len(v):9.4f} {sum(v) / tot:6.1%}")
+    steps = [x for k, v in agg.items() if "k_step" in k for x in v]
+    if steps:
+        print(f"all step-kernel launches: {len(steps)}, mean {sum(steps) / len(steps):.4f} ms")
+        last = sorted(((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+                       for r in rows if "k_step" in r["Kernel_Name"]))
+        return last
+    return None
+
+
+KERNEL_SOURCES = ("paper_1807_04733_amd/csrc/pic_kernels.hip",
+                  "paper_1807_04733_amd/csrc/pic_device.h",
+                  "paper_1807_04733_amd/csrc/pic_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_hbm_traffic.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (otherwise None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("kernel_source") != kernel_source_hash():
+        return None
+    fetch = float(vals["fetch_kib"]) * float(vals["fetch_scale"]) * 1024
+    write = float(vals["write_kib"]) * float(vals["write_scale"]) * 1024
+    return fetch + write
+
+
+def summarize_pmc(path: str, last: int):
+    """Mean of each counter per step-kernel dispatch over the last `last` dispatches of a
+    rocprofv3 --pmc CSV (and the same for every other kernel)."""
+    import csv
+    import collections
+
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    name = {}
+    for r in csv.DictReader(open(path)):
+        d = int(r["Dispatch_Id"])
+        per[d][r["Counter_Name"]] += float(r["Counter_Value"])
+        name[d] = r["Kernel_Name"]
+    steps = sorted(d for d in per if "k_step" in name[d])
+    sel = steps[-last:] if last else steps
+    counters = sorted({c for d in sel for c in per[d]})
+    print(f"step-kernel dispatches averaged: {len(sel)} (of {len(steps)})")
+    for c in counters:
+        print(f"  {c}: {sum(per[d][c] for d in sel) / len(sel):.6g} per dispatch")
+    for k in sorted(set(name.values())):
+        if "k_step" in k:
+            continue
+        ds = [d for d in per if name[d] == k]
+        for c in counters:
+            vals = [per[d][c] for d in ds if c in per[d]]
+            if vals:
+                print(f"  [{k[:48]}] {c}: {sum(vals) / len(vals):.6g} per dispatch ({len(vals)})")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,7 +281,32 @@ def main():
                     help="steps per autotuning trial (0: keep the default launch shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--adjoint-primaries", type=int, default=100_000_000,
+                    help="primaries of the forward+adjoint leg (0: skip)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip running the batched stacks one by one")
+    ap.add_argument("--summarize-pmc", default="",
+                    help="print per-dispatch counter means of a rocprofv3 --pmc CSV and exit")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the step kernel's sources and exit")
+    ap.add_argument("--summarize-trace", default="",
+                    help="print per-kernel statistics of a rocprofv3 kernel-trace CSV and exit")
+    ap.add_argument("--last-launches", type=int, default=0,
+                    help="with --summarize-trace: also report the mean of the last N step launches")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.last_launches)
+        return
+    if args.summarize_trace:
+        last = summarize_trace(args.summarize_trace)
+        if last and args.last_launches:
+            tail = [d for _, d in last[-args.last_launches:]]
+            print(f"last {len(tail)} step-kernel launches (the HIP-event timing run): "
+                  f"mean {sum(tail) / len(tail):.4f} ms")
+        return
     if args.copy_calibration:
         import torch
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
@@ -189,17 +368,32 @@ def main():
         assert np.array_equal(cnt2, cnt), "step-by-step run differs from the graph run"
         b = alg_bytes(cnt2, prob.state_fp64)
         achieved = b.sum() / (ms.sum() * 1e-3) / 1e9
+        traffic = measured_traffic() if args.workload == "batched" else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic, 0))
         extra["step_kernel"] = dict(launches=int(prob.n_steps),
                                     mean_launch_ms=round(float(ms.mean()), 4),
                                     alg_bytes_per_launch=float(b.mean()),
                                     bytes_per_particle_step=round(float(b.sum() / ps), 2),
+                                    kernel_source=kernel_source_hash(),
                                     compaction_ms_per_run=round(comp_ms, 3))
         print(f"[bench] step kernel: {ms.mean():.4f} ms/launch, {achieved:.1f} GB/s algorithmic",
               file=sys.stderr, flush=True)
     extra["tuning"] = sim.tuning()
     sim.close()
+    torch.cuda.empty_cache()
+    if args.workload == "batched" and not args.no_sequential:
+        print("[bench] running the stacks one by one", file=sys.stderr, flush=True)
+        extra["sequential"] = sequential_leg(prob, wall / args.steps)
+        print(f"[bench] sequential: {extra['sequential']}", file=sys.stderr, flush=True)
+    if args.adjoint_primaries > 0:
+        print("[bench] forward + adjoint leg", file=sys.stderr, flush=True)
+        try:
+            extra["adjoint"] = adjoint_leg(args.adjoint_primaries, args.tune_steps)
+        except Exception as e:  # reported, never hidden
+            extra["adjoint"] = {"error": str(e)}
+        print(f"[bench] adjoint: {extra['adjoint']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
