@@ -139,6 +139,80 @@ __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& m
   z = ze;
 }
 
+// Table values of a carrier's (layer, spin), kept in registers through the step and
+// reloaded from LDS only when the carrier changes layer.
+struct LayCache {
+  double zlo, zhi, v, itau;
+};
+
+__device__ __forceinline__ LayCache load_lay(const DevInst& I, int l, int s) {
+  const double2 C = I.chan[l][s];
+  return LayCache{I.lay[l].x, I.lay[l].y, C.x, C.y};
+}
+
+// Transport half step with the layer's table values cached (same arithmetic and draws
+// as half_push).
+__device__ __forceinline__ void half_push_c(const DevInst& I, LayCache& c, double& z, double& mu,
+                                            uint32_t& fl, uint32_t E, uint32_t lo, uint32_t hi,
+                                            uint32_t step, uint32_t tag, double h, uint32_t k0,
+                                            uint32_t k1, HitCounts& hc, bool& bad) {
+  double ze = z + (c.v * mu) * h;
+  if (ze > c.zhi || ze < c.zlo) {
+    int l = layer_of(fl);
+    const int s = (int)(fl & kSpinMask);
+    uint32_t draws = 0;
+    for (int hit = 0;; ++hit) {
+      const bool up = ze > c.zhi;
+      if (!up && !(ze < c.zlo)) break;
+      if (hit == kMaxHits) {
+        bad = true;
+        ze = up ? c.zhi : c.zlo;
+        break;
+      }
+      const double b = up ? c.zhi : c.zlo;
+      const bool outer = up ? (l == I.n_layers - 1) : (l == 0);
+      if (outer) {
+        ze = b - (ze - b);
+        mu = -mu;
+        ++hc.rs;
+        continue;
+      }
+      const int iface = up ? l : l - 1;
+      const int nl = up ? l + 1 : l - 1;
+      const double T = trans_prob(I, I.tt[iface][up ? 0 : 1][s], E);
+      bool go;
+      if (T >= 1.0) {
+        go = true;
+      } else if (T <= 0.0) {
+        go = false;
+      } else {
+        const uint4 w = philox10(lo, hi, step, tag + draws, k0, k1);
+        go = u01(w.x) < T;
+      }
+      ++draws;
+      if (go) {
+        const double r = I.ratio[l][s][up ? 0 : 1];
+        ze = b + (ze - b) * r;
+        l = nl;
+        c = load_lay(I, l, s);
+        ++hc.tr;
+      } else {
+        ze = b - (ze - b);
+        mu = -mu;
+        ++hc.ri;
+      }
+    }
+    fl = (fl & ~(kLayerMask << kLayerShift)) | ((uint32_t)l << kLayerShift);
+  }
+  z = ze;
+}
+
+// Number of set bits of a wave mask in the lanes below this one.
+__device__ __forceinline__ int prefix_count(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ int energy_bin(const uint32_t* edges, int n, uint32_t E) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {

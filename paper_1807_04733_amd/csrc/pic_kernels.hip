@@ -32,7 +32,7 @@ constexpr int kModeCur = 8;         // this step deposits the current
 template <int MODE>
 __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
                                         unsigned long long* s_cur, const uint32_t* s_edges,
-                                        double z, double mu, uint32_t E, uint32_t fl) {
+                                        double z, double mu, uint32_t E, uint32_t fl, double v) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
@@ -47,7 +47,7 @@ __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uin
     }
   }
   if (MODE & kModeCur) {
-    const double vm = I.chan[layer_of(fl)][s].x * mu;
+    const double vm = v * mu;
     // round-half-even to an integer by adding 1.5*2^52 (|vm*2^32| < 2^51): the low
     // mantissa bits then hold the integer, identical to rint()
     const double sh = vm * 4294967296.0 + 0x1.8p52;
@@ -103,6 +103,17 @@ struct ChildQueue {  // kChildQueueBytes
   uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ];
 };
 
+// The SoA arrays offset to one slab: uniform base pointers with 32-bit lane offsets.
+template <typename F>
+struct SlabPtrs {
+  F* z;
+  F* mu;
+  uint32_t* E;
+  uint64_t* uid;
+  uint32_t* fl;
+  uint64_t* ev;
+};
+
 struct LaneCounts {
   uint32_t dep, tr, ri, rs;
 };
@@ -113,8 +124,8 @@ template <typename F, int MODE>
 __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst& I, ChildQueue& Q,
                                                int qn, int n, uint32_t* s_dens,
                                                unsigned long long* s_cur, const uint32_t* s_edges,
-                                               int* s_app, int64_t base, int tail0, int cap,
-                                               LaneCounts& lc, bool& bad) {
+                                               int* s_app, const SlabPtrs<F>& sp, int tail0,
+                                               int cap, LaneCounts& lc, bool& bad) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   const int lane = __lane_id();
   const bool act = lane < n;
@@ -133,9 +144,11 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
     }
     uint32_t cfl = cs | (pfl & ~kSpinMask);
     HitCounts h{0, 0, 0};
-    half_push(I, cz, cmu, cfl, cE, lo, lin, (uint32_t)a.step, kTagHalf2, a.h, a.key0, a.key1, h, bad);
+    LayCache cc = load_lay(I, l, (int)cs);
+    half_push_c(I, cc, cz, cmu, cfl, cE, lo, lin, (uint32_t)a.step, kTagHalf2, a.h, a.key0,
+                a.key1, h, bad);
     cz = to_store<F>(cz);
-    deposit<MODE>(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl);
+    deposit<MODE>(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl, cc.v);
     lc.dep += 1;
     lc.tr += h.tr;
     lc.ri += h.ri;
@@ -145,15 +158,14 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
     const int leader = __ffsll((unsigned long long)m) - 1;
     if (lane == leader) off = atomicAdd(s_app, __popcll(m));
     off = __shfl(off, leader);
-    const int pos = tail0 + off + __popcll(m & lanes_below());
-    if (pos < cap) {
-      const int64_t g = base + pos;
-      ((F*)a.z)[g] = (F)cz;
-      ((F*)a.mu)[g] = (F)cmu;
-      a.E[g] = cE;
-      a.uid[g] = (uint64_t)lo | ((uint64_t)lin << 32);
-      a.flags[g] = cfl;
-      if (DEBUG) a.ev[g] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
+    const uint32_t pos = (uint32_t)(tail0 + off + prefix_count(m));
+    if ((int)pos < cap) {
+      sp.z[pos] = (F)cz;
+      sp.mu[pos] = (F)cmu;
+      sp.E[pos] = cE;
+      sp.uid[pos] = (uint64_t)lo | ((uint64_t)lin << 32);
+      sp.fl[pos] = cfl;
+      if (DEBUG) sp.ev[pos] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
     } else {
       atomicOr(a.status, kStOverflow);
     }
@@ -161,7 +173,7 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
 }
 
 template <typename F, int MODE>
-__global__ void __launch_bounds__(512) k_step(StepArgs a) {
+__global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   // dynamic LDS: [density histogram | current histogram | one child queue per wave]
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -219,6 +231,8 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
     const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
     const int total = tail0 + n_inj;
     if (tid == 0 && n_inj) atomicAdd(&s_cnt[PIC_C_INJECTED], (unsigned long long)n_inj);
+    const SlabPtrs<F> sp{gz + base, gmu + base, a.E + base, a.uid + base, a.flags + base,
+                         DEBUG ? a.ev + base : nullptr};
     LaneCounts lc{0, 0, 0, 0};
     int qn = 0;  // wave-uniform fill of this wave's child queue
 
@@ -230,13 +244,13 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
     uint64_t nu = 0, nev = 0;
     auto fetch = [&](int t) {
       if (t < tail0) {
-        const int64_t g = base + t;
-        nfl = a.flags[g];
-        nz = gz[g];
-        nmu = gmu[g];
-        nE = a.E[g];
-        nu = a.uid[g];
-        if (DEBUG) nev = a.ev[g];
+        const uint32_t g = (uint32_t)t;
+        nfl = sp.fl[g];
+        nz = sp.z[g];
+        nmu = sp.mu[g];
+        nE = sp.E[g];
+        nu = sp.uid[g];
+        if (DEBUG) nev = sp.ev[g];
       } else {
         nfl = kDead;
       }
@@ -251,7 +265,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
       const bool have = t < total;
       const bool from_soa = have && t < tail0;
       const bool is_new = have && !from_soa;
-      const int64_t gi = base + t;
+      const uint32_t gi = (uint32_t)t;
       double z = 0.0, mu = 0.0;
       uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
       uint64_t evp = 0;
@@ -295,15 +309,14 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
       if (alive0) {
         const double mu_in = mu;
         const uint32_t fl_in = fl;
-        half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad);
+        LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
+        half_push_c(I, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad);
         // ---- scattering over the full step, at the mid-step state
         const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
-        const int l = layer_of(fl);
-        const int s = (int)(fl & kSpinMask);
         const double E_ev = (double)E * 0x1p-30;
         const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-        const double itel = I.lay[l].z;
-        const double rate = Ek * I.chan[l][s].y + itel;
+        const double itel = I.lay[layer_of(fl)].z;
+        const double rate = Ek * c.itau + itel;
         const double x = a.dt * rate;
         const double u0 = u01(w.x);
         // event iff u0 < p = 1 - exp(-x), decided without the transcendental outside a
@@ -349,9 +362,9 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
           }
         }
         if (!died) {
-          half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
+          half_push_c(I, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
           z = to_store<F>(z);
-          deposit<MODE>(a, I, s_dens, s_cur, s_edges, z, mu, E, fl);
+          deposit<MODE>(a, I, s_dens, s_cur, s_edges, z, mu, E, fl, c.v);
           lc.dep += 1;
         } else {
           z = to_store<F>(z);
@@ -367,10 +380,9 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
 
       // ---- queue the newborns: (mid-step position, parent uid, energy, layer | gen)
       const uint64_t mq = __ballot(spawn);
-      const uint64_t below = lanes_below();
       if (mq) {
         if (spawn) {
-          const int p = qn + __popcll(mq & below);
+          const int p = qn + prefix_count(mq);
           uint32_t gen = (flmid >> kGenShift) & kGenMask;
           gen = gen < 255u ? gen + 1u : 255u;
           Q.z[p] = zmid;
@@ -389,26 +401,25 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
         if (lane == leader) off = atomicAdd(&s_app, __popcll(ma));
         off = __shfl(off, leader);
         if (is_new) {
-          const int pos = tail0 + off + __popcll(ma & below);
-          if (pos < cap) {
-            const int64_t g = base + pos;
-            gz[g] = (F)z;
-            gmu[g] = (F)mu;
-            a.E[g] = E;
-            a.uid[g] = (uint64_t)lo | ((uint64_t)hi << 32);
-            a.flags[g] = fl;
-            if (DEBUG) a.ev[g] = evp;
+          const uint32_t pos = (uint32_t)(tail0 + off + prefix_count(ma));
+          if ((int)pos < cap) {
+            sp.z[pos] = (F)z;
+            sp.mu[pos] = (F)mu;
+            sp.E[pos] = E;
+            sp.uid[pos] = (uint64_t)lo | ((uint64_t)hi << 32);
+            sp.fl[pos] = fl;
+            if (DEBUG) sp.ev[pos] = evp;
           } else {
             atomicOr(a.status, kStOverflow);
           }
         }
       }
       if (from_soa && alive0) {
-        gz[gi] = (F)z;
-        if (dirty & 1u) gmu[gi] = (F)mu;
-        if (dirty & 2u) a.E[gi] = E;
-        if (dirty & 4u) a.flags[gi] = fl;
-        if (DEBUG) a.ev[gi] = evp;
+        sp.z[gi] = (F)z;
+        if (dirty & 1u) sp.mu[gi] = (F)mu;
+        if (dirty & 2u) sp.E[gi] = E;
+        if (dirty & 4u) sp.fl[gi] = fl;
+        if (DEBUG) sp.ev[gi] = evp;
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
@@ -416,7 +427,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        drain_children<F, MODE>(a, I, Q, qn, 64, s_dens, s_cur, s_edges, &s_app, base, tail0,
+        drain_children<F, MODE>(a, I, Q, qn, 64, s_dens, s_cur, s_edges, &s_app, sp, tail0,
                                 cap, lc, bad);
         qn -= 64;
         __builtin_amdgcn_wave_barrier();
@@ -426,7 +437,7 @@ __global__ void __launch_bounds__(512) k_step(StepArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      drain_children<F, MODE>(a, I, Q, qn, qn, s_dens, s_cur, s_edges, &s_app, base, tail0, cap,
+      drain_children<F, MODE>(a, I, Q, qn, qn, s_dens, s_cur, s_edges, &s_app, sp, tail0, cap,
                               lc, bad);
       __builtin_amdgcn_wave_barrier();
     }
