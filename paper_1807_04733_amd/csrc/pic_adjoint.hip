@@ -124,7 +124,7 @@ struct HitScore {
 // g of its current bin times v*cos(theta) (the fixed-point value the forward deposits).
 __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst& I, double z,
                                                  double mu, uint32_t E, uint32_t fl,
-                                                 const uint32_t* s_edges) {
+                                                 const uint32_t* s_edges, const double* s_gcur) {
   const StepArgs& a = A.s;
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
@@ -135,7 +135,7 @@ __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst
     g += A.g_dens[I.dens_off + (((int64_t)a.dens_slot * I.nz + zb) * a.n_ebins + eb) * 2 + s];
   }
   if (a.cur_on && A.g_cur) {
-    const double gc = A.g_cur[I.cur_off + ((int64_t)a.cur_slot * I.nz + zb) * 2 + s];
+    const double gc = s_gcur[zb * 2 + s];
     if (gc != 0.0) {
       const double vm = I.chan[layer_of(fl)][s].x * mu;
       const double sh = vm * 4294967296.0 + 0x1.8p52;
@@ -172,8 +172,10 @@ __device__ __forceinline__ int append_slot(bool want, int* s_app, int tail0) {
 }
 
 template <typename F, int ADJ>
-__global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
+__global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
   const StepArgs& a = A.s;
+  // this step's slice of dL/d(current) for the workgroup's instance (dynamic LDS)
+  extern __shared__ double s_gcur[];
   __shared__ DevInst s_inst;
   __shared__ double s_grad[kMaxK];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
@@ -199,6 +201,11 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
       const uint4* src = (const uint4*)&a.inst[inst];
       uint4* dst = (uint4*)&s_inst;
       for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
+      if (a.cur_on && A.g_cur) {
+        const DevInst& Ig = a.inst[inst];
+        const double* gsl = A.g_cur + Ig.cur_off + (int64_t)a.cur_slot * Ig.nz * 2;
+        for (int i = tid; i < Ig.nz * 2; i += blockDim.x) s_gcur[i] = gsl[i];
+      }
       cur_inst = inst;
     }
     if (tid == 0) {
@@ -217,8 +224,29 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
     const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
     const int total = tail0 + n_inj;
 
+    // next slot of this lane, fetched one iteration ahead (as in the forward step)
+    F nz = 0, nmu = 0;
+    uint32_t nE = 0, nfl = kDead;
+    uint64_t nu = 0;
+    auto fetch = [&](int t) {
+      if (t < tail0) {
+        const int64_t g = base + t;
+        nfl = a.flags[g];
+        nz = gz[g];
+        nmu = gmu[g];
+        nE = a.E[g];
+        nu = a.uid[g];
+      } else {
+        nfl = kDead;
+      }
+    };
+    fetch(wave * 64 + lane);
     for (int tb = wave * 64; tb < total; tb += blockDim.x) {
       const int t = tb + lane;
+      const F rz = nz, rmu = nmu;
+      const uint32_t rE = nE, rfl = nfl;
+      const uint64_t ru = nu;
+      fetch(t + (int)blockDim.x);
       const bool have = t < total;
       const bool from_soa = have && t < tail0;
       const bool is_new = have && !from_soa;
@@ -234,14 +262,13 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
       double z = 0.0, mu = 0.0;
       uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
       if (from_soa) {
-        fl = a.flags[gi];
+        fl = rfl;
         if (!(fl & kDead)) {
-          z = (double)gz[gi];
-          mu = (double)gmu[gi];
-          E = a.E[gi];
-          const uint64_t u = a.uid[gi];
-          lo = (uint32_t)u;
-          hi = (uint32_t)(u >> 32);
+          z = (double)rz;
+          mu = (double)rmu;
+          E = rE;
+          lo = (uint32_t)ru;
+          hi = (uint32_t)(ru >> 32);
         }
       } else if (is_new && room) {
         const int64_t j = kk + S * (f0 + (t - tail0));
@@ -269,6 +296,8 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
       const bool alive0 = !(fl & kDead);
       bool died = false;
       AdjLane L{gi, lo, 0.0, false};
+      const double mu_in = mu;
+      const uint32_t E_in = E, fl_in = fl;
       if (alive0) {
         HitCounts hc{0, 0, 0};
         {
@@ -331,7 +360,7 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
                             chc, bad, hs);
                 }
                 cz = to_store<F>(cz);
-                const double g = deposit_weight(A, I, cz, cmu, E2, cfl, s_edges);
+                const double g = deposit_weight(A, I, cz, cmu, E2, cfl, s_edges, s_gcur);
                 on_deposit<ADJ>(ops, a, I, CL, cfl, E2, g, step);
                 gz[cg] = (F)cz;
                 gmu[cg] = (F)cmu;
@@ -351,7 +380,7 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
             half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad, hs);
           }
           z = to_store<F>(z);
-          const double g = deposit_weight(A, I, z, mu, E, fl, s_edges);
+          const double g = deposit_weight(A, I, z, mu, E, fl, s_edges, s_gcur);
           on_deposit<ADJ>(ops, a, I, L, fl, E, g, step);
         } else {
           z = to_store<F>(z);
@@ -361,12 +390,17 @@ __global__ void __launch_bounds__(256) k_adj(AdjArgs A) {
             if (r != 0.0) atomicAdd(&A.R[lo], r);
           }
         }
-        if ((from_soa || room) && have) {
+        if (is_new) {
           gz[gi] = (F)z;
           gmu[gi] = (F)mu;
           a.E[gi] = E;
           a.flags[gi] = fl;
-          if (is_new) a.uid[gi] = (uint64_t)lo | ((uint64_t)hi << 32);
+          a.uid[gi] = (uint64_t)lo | ((uint64_t)hi << 32);
+        } else {
+          gz[gi] = (F)z;
+          if (mu != mu_in) gmu[gi] = (F)mu;
+          if (E != E_in) a.E[gi] = E;
+          if (fl != fl_in) a.flags[gi] = fl;
         }
       }
       const uint64_t md = __ballot(died);
@@ -429,10 +463,11 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs A, uint32_t n_steps) 
 
 template <typename F>
 static hipError_t launch_adj_prec(const AdjArgs& A, int adj, int grid, int block, hipStream_t s) {
+  const size_t lds = (size_t)A.s.lds_cur_words * 8;
   switch (adj) {
-    case 1: hipLaunchKernelGGL((k_adj<F, 1>), dim3(grid), dim3(block), 0, s, A); break;
-    case 2: hipLaunchKernelGGL((k_adj<F, 2>), dim3(grid), dim3(block), 0, s, A); break;
-    case 3: hipLaunchKernelGGL((k_adj<F, 3>), dim3(grid), dim3(block), 0, s, A); break;
+    case 1: hipLaunchKernelGGL((k_adj<F, 1>), dim3(grid), dim3(block), lds, s, A); break;
+    case 2: hipLaunchKernelGGL((k_adj<F, 2>), dim3(grid), dim3(block), lds, s, A); break;
+    case 3: hipLaunchKernelGGL((k_adj<F, 3>), dim3(grid), dim3(block), lds, s, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -332,6 +332,9 @@ CompactArgs compact_args(const pic_ctx* c) {
   a.slab_dead = c->at<int32_t>(p.off_slab_dead);
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.frac = c->tune.compact_frac;
+  a.S = nullptr;
+  a.K = 0;
+  a.r = nullptr;
   return a;
 }
 
@@ -666,9 +669,17 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
   A.grad = c->at<double>(p.off_grad);
   A.K = p.K;
   A.n_ch = c->inst[0].n_channels;
+  CompactArgs ca = compact_args(c);
+  ca.S = adj == 1 ? A.S : nullptr;
+  ca.K = adj == 1 ? p.K : 0;
+  ca.r = adj == 2 ? A.r : nullptr;
   for (int n = 0; n < c->cfg.n_steps; ++n) {
     A.s = step_args(c, n);
     HIP_TRY(launch_adjoint(A, fp64, adj, grid, block, c->stream));
+    // carriers move with their score rows (causal) or partial returns (tree pass 1)
+    if (c->tune.compact_every > 0 && (n + 1) % c->tune.compact_every == 0 &&
+        n + 1 < c->cfg.n_steps)
+      HIP_TRY(launch_compact(ca, fp64, 256, c->stream));
   }
   A.s = step_args(c, c->cfg.n_steps - 1);
   HIP_TRY(launch_adjoint_final(A, fp64, adj, (uint32_t)c->cfg.n_steps, c->stream));

@@ -113,6 +113,9 @@ struct CompactArgs {
   int32_t* slab_dead;
   int32_t n_slabs;
   float frac;
+  double* S;                   // adjoint score rows [capacity][K] moved along, or null
+  int32_t K;
+  double* r;                   // adjoint partial returns moved along, or null
 };
 
 // bytes of one wave's newborn queue in dynamic LDS (see pic_kernels.hip)

@@ -485,12 +485,20 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
     F z = 0, mu = 0;
     uint32_t E = 0;
     uint64_t u = 0, ev = 0;
+    double row[kMaxCausalK];
+    double rr = 0.0;
     if (keep) {
       z = gz[base + t];
       mu = gmu[base + t];
       E = a.E[base + t];
       u = a.uid[base + t];
       if (a.ev) ev = a.ev[base + t];
+      if (a.S) {
+#pragma unroll
+        for (int k = 0; k < kMaxCausalK; ++k)
+          if (k < a.K) row[k] = a.S[(base + t) * a.K + k];
+      }
+      if (a.r) rr = a.r[base + t];
     }
     const uint64_t m = __ballot(keep);
     if (lane == 0) s_w[wave] = __popcll(m);
@@ -509,6 +517,12 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
       a.uid[d] = u;
       a.flags[d] = fl;
       if (a.ev) a.ev[d] = ev;
+      if (a.S) {
+#pragma unroll
+        for (int k = 0; k < kMaxCausalK; ++k)
+          if (k < a.K) a.S[d * a.K + k] = row[k];
+      }
+      if (a.r) a.r[d] = rr;
     }
     out += tot;
     __syncthreads();
