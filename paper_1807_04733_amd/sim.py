@@ -237,8 +237,11 @@ class PicSim:
             oc += nc
         return dens, cur
 
-    def particles(self, include_dead: bool = True) -> dict:
-        """Copy the particle state out of the workspace (for inspection and tests)."""
+    def particles(self, include_dead: bool = True, roots_below: Optional[int] = None) -> dict:
+        """Copy the particle state out of the workspace (for inspection and tests).
+
+        roots_below=R keeps only the carriers of each instance's first R primary trees
+        (selected on the device, so that full-size runs can be sampled)."""
         import torch
 
         self.stream.synchronize()
@@ -253,13 +256,25 @@ class PicSim:
         base = arr(lay.off_slab_base, ns, torch.int64).cpu().numpy()
         tail = arr(lay.off_slab_tail, ns, torch.int32).cpu().numpy()
         inst = arr(lay.off_slab_inst, ns, torch.int32).cpu().numpy()
-        idx = np.concatenate([np.arange(b, b + t, dtype=np.int64) for b, t in zip(base, tail)]
-                             + [np.zeros(0, np.int64)])
-        slab_of = np.repeat(np.arange(ns), tail)
         fdt = torch.float64 if lay.state_bytes == 8 else torch.float32
         cap = lay.capacity
-        ti = torch.from_numpy(idx).to(self.device)
-        torch.cuda.current_stream(self.device).synchronize()
+        with torch.cuda.stream(self.stream):
+            tb = torch.from_numpy(base).to(self.device)
+            tt = torch.from_numpy(tail.astype(np.int64)).to(self.device)
+            slab_of = torch.repeat_interleave(torch.arange(ns, device=self.device), tt)
+            start = torch.cumsum(tt, 0) - tt
+            ti = tb[slab_of] + (torch.arange(slab_of.numel(), device=self.device) - start[slab_of])
+            if roots_below is not None:
+                offs = torch.tensor([it.root_offset for it in self.problem.instances],
+                                    dtype=torch.int64, device=self.device)
+                uid = arr(lay.off_uid, cap, torch.int64)[ti]
+                root = uid & 0xFFFFFFFF
+                inst_t = torch.from_numpy(inst.astype(np.int64)).to(self.device)[slab_of]
+                keep = (root - offs[inst_t]) < roots_below
+                ti = ti[keep]
+                slab_of = slab_of[keep]
+        self.stream.synchronize()
+        slab_of = slab_of.cpu().numpy()
         z = arr(lay.off_z, cap, fdt)[ti].double().cpu().numpy()
         mu = arr(lay.off_mu, cap, fdt)[ti].double().cpu().numpy()
         E = arr(lay.off_E, cap, torch.int32)[ti].cpu().numpy().view(np.uint32)
@@ -279,6 +294,26 @@ class PicSim:
             keep = ~out["dead"]
             out = {k: v[keep] for k, v in out.items()}
         return out
+
+    def alive_energy(self) -> int:
+        """Sum of the fixed-point energies of all live carriers (inspection helper)."""
+        import torch
+
+        self.stream.synchronize()
+        lay = self.layout
+        with torch.cuda.stream(self.stream):
+            E = self.ws[lay.off_E:lay.off_E + 4 * lay.capacity].view(torch.int32)
+            fl = self.ws[lay.off_flags:lay.off_flags + 4 * lay.capacity].view(torch.int32)
+            base = self.ws[lay.off_slab_base:lay.off_slab_base + 8 * lay.n_slabs].view(torch.int64)
+            tail = self.ws[lay.off_slab_tail:lay.off_slab_tail + 4 * lay.n_slabs].view(torch.int32)
+            tt = tail.to(torch.int64)
+            slab_of = torch.repeat_interleave(torch.arange(lay.n_slabs, device=self.device), tt)
+            start = torch.cumsum(tt, 0) - tt
+            ti = base[slab_of] + (torch.arange(slab_of.numel(), device=self.device) - start[slab_of])
+            live = fl[ti] >= 0                      # dead bit is the sign bit
+            tot = (E[ti].to(torch.int64) & 0xFFFFFFFF)[live].sum()
+        self.stream.synchronize()
+        return int(tot.item())
 
     def close(self):
         if self.handle:
