@@ -249,7 +249,7 @@ size_t lds_for(const pic_ctx* c, int block, bool dens_step) {
   const size_t dens = dens_step && c->dens_lds ? (size_t)c->lds_dens_words * 4 : 0;
   const size_t cur_at = (dens + 15) & ~(size_t)15;
   const size_t q_at = (cur_at + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
-  return q_at + (size_t)(block / 64) * kChildQueueBytes;
+  return q_at + (size_t)(block / 64) * (kChildQueueBytes + kSlowQueueBytes);
 }
 
 // Largest dynamic LDS a step launch may use: the device's per-workgroup limit minus the

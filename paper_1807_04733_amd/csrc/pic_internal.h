@@ -118,8 +118,9 @@ struct CompactArgs {
   double* r;                   // adjoint partial returns moved along, or null
 };
 
-// bytes of one wave's newborn queue in dynamic LDS (see pic_kernels.hip)
+// bytes of one wave's newborn queue and general-path slot queue in dynamic LDS
 constexpr size_t kChildQueueBytes = 128 * (8 + 4 * 4);
+constexpr size_t kSlowQueueBytes = 128 * 4;
 
 // launchers (pic_kernels.hip)
 hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,

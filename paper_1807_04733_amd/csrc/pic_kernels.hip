@@ -172,15 +172,24 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
   }
 }
 
+// Slots whose step needs the general path (a boundary hit, or a draw below x that may be
+// an event) wait in a wave-private LDS queue; their state is still untouched in HBM and
+// is re-read when 64 have gathered, so the general path runs as full waves while the
+// common step (no hit, certainly no event) runs without divergent branches.
+constexpr int kSlowQ = 128;
+
 template <typename F, int MODE>
 __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  // dynamic LDS: [density histogram | current histogram | one child queue per wave]
+  // dynamic LDS: [density histogram | current histogram | child queue per wave |
+  //               general-path slot queue per wave]
   extern __shared__ __align__(16) unsigned char dyn[];
   uint32_t* s_dens = (uint32_t*)dyn;
   const size_t cur_at = ((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15;
   unsigned long long* s_cur = (unsigned long long*)(dyn + cur_at);
-  ChildQueue* s_q = (ChildQueue*)(dyn + ((cur_at + (size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15));
+  const size_t q_at = (cur_at + (size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15;
+  ChildQueue* s_q = (ChildQueue*)(dyn + q_at);
+  uint32_t* s_slow = (uint32_t*)(dyn + q_at + (size_t)(blockDim.x >> 6) * kChildQueueBytes);
   __shared__ DevInst s_inst;
   __shared__ unsigned long long s_cnt[kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
@@ -198,6 +207,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   F* gmu = (F*)a.mu;
   const uint32_t step = (uint32_t)a.step;
   ChildQueue& Q = s_q[wave];
+  uint32_t* SQ = s_slow + wave * kSlowQ;
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   int cur_inst = -1;
   bool bad = false;
@@ -235,71 +245,15 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                          DEBUG ? a.ev + base : nullptr};
     LaneCounts lc{0, 0, 0, 0};
     int qn = 0;  // wave-uniform fill of this wave's child queue
+    int sn = 0;  // wave-uniform fill of this wave's general-path queue
 
-    // The slot a lane will handle in its next iteration is fetched one iteration ahead,
-    // unconditionally (a dead slot's fields are loaded too), so that no load waits on
-    // another and each wave keeps two particles' worth of loads in flight.
-    F nz = 0, nmu = 0;
-    uint32_t nE = 0, nfl = kDead;
-    uint64_t nu = 0, nev = 0;
-    auto fetch = [&](int t) {
-      if (t < tail0) {
-        const uint32_t g = (uint32_t)t;
-        nfl = sp.fl[g];
-        nz = sp.z[g];
-        nmu = sp.mu[g];
-        nE = sp.E[g];
-        nu = sp.uid[g];
-        if (DEBUG) nev = sp.ev[g];
-      } else {
-        nfl = kDead;
-      }
-    };
-    fetch(wave * 64 + lane);
-    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
-      const int t = tb + lane;
-      const F rz = nz, rmu = nmu;
-      const uint32_t rE = nE, rfl = nfl;
-      const uint64_t ru = nu, rev = nev;
-      fetch(t + (int)blockDim.x);
-      const bool have = t < total;
-      const bool from_soa = have && t < tail0;
-      const bool is_new = have && !from_soa;
-      const uint32_t gi = (uint32_t)t;
-      double z = 0.0, mu = 0.0;
-      uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
-      uint64_t evp = 0;
-      if (from_soa) {
-        fl = rfl;
-        if (!(fl & kDead)) {
-          z = (double)rz;
-          mu = (double)rmu;
-          E = rE;
-          lo = (uint32_t)ru;
-          hi = (uint32_t)(ru >> 32);
-          evp = rev;
-        }
-      } else if (is_new) {
-        // Source term: one primary per root, Eq. (17)
-        const int64_t j = kk + S * (f0 + (t - tail0));
-        const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
-        const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
-        double z0;
-        if (I.src_lambda > 0.0)
-          z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
-        else
-          z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
-        z = to_store<F>(z0);
-        mu = to_store<F>(dircos(w.y));
-        const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
-        E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
-        int l = 0;
-        for (int q = 1; q < I.n_layers; ++q)
-          if (I.lay[q].x <= z) l = q;
-        fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift);
-        lo = root;
-        hi = 0;
-      }
+    // ---------------------------------------------------------------- general path
+    // The whole step for one carrier: boundary hits, the exact scattering decision,
+    // elastic / inelastic events, absorption, the newborn's queueing, the append of a
+    // new primary and the write-back.  All lanes of the wave call it together; lanes
+    // with nothing to do pass a dead carrier.
+    auto general = [&](bool from_soa, bool is_new, uint32_t gi, double z, double mu,
+                       uint32_t E, uint32_t fl, uint32_t lo, uint32_t hi, uint64_t evp) {
       const bool alive0 = !(fl & kDead);
       bool died = false, spawn = false;
       uint32_t dirty = 0;  // 1: mu, 2: E, 4: flags
@@ -423,24 +377,138 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
-      if (qn >= 64) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        drain_children<F, MODE>(a, I, Q, qn, 64, s_dens, s_cur, s_edges, &s_app, sp, tail0,
-                                cap, lc, bad);
-        qn -= 64;
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    if (qn > 0) {
+    };
+
+    auto wave_sync = [&]() {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      drain_children<F, MODE>(a, I, Q, qn, qn, s_dens, s_cur, s_edges, &s_app, sp, tail0, cap,
+    };
+    // finish the top n queued general-path slots (state re-read from HBM)
+    auto drain_slow = [&](int n) {
+      wave_sync();
+      const bool act = lane < n;
+      const uint32_t g = act ? SQ[sn - n + lane] : 0u;
+      sn -= n;
+      uint32_t fl = kDead, E = 0, lo = 0, hi = 0;
+      double z = 0.0, mu = 0.0;
+      uint64_t evp = 0;
+      if (act) {
+        fl = sp.fl[g];
+        z = (double)sp.z[g];
+        mu = (double)sp.mu[g];
+        E = sp.E[g];
+        const uint64_t u = sp.uid[g];
+        lo = (uint32_t)u;
+        hi = (uint32_t)(u >> 32);
+        if (DEBUG) evp = sp.ev[g];
+      }
+      general(act, false, g, z, mu, E, fl, lo, hi, evp);
+      wave_sync();
+    };
+    auto drain_kids = [&](int n) {
+      wave_sync();
+      drain_children<F, MODE>(a, I, Q, qn, n, s_dens, s_cur, s_edges, &s_app, sp, tail0, cap,
                               lc, bad);
-      __builtin_amdgcn_wave_barrier();
+      qn -= n;
+      wave_sync();
+    };
+
+    // The slot a lane will handle in its next iteration is fetched one iteration ahead,
+    // unconditionally (a dead slot's fields are loaded too), so that no load waits on
+    // another and each wave keeps two particles' worth of loads in flight.
+    F nz = 0, nmu = 0;
+    uint32_t nE = 0, nfl = kDead;
+    uint64_t nu = 0;
+    auto fetch = [&](int t) {
+      if (t < tail0) {
+        const uint32_t g = (uint32_t)t;
+        nfl = sp.fl[g];
+        nz = sp.z[g];
+        nmu = sp.mu[g];
+        nE = sp.E[g];
+        nu = sp.uid[g];
+      } else {
+        nfl = kDead;
+      }
+    };
+    fetch(wave * 64 + lane);
+    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
+      const int t = tb + lane;
+      const F rz = nz, rmu = nmu;
+      const uint32_t rE = nE, rfl = nfl;
+      const uint64_t ru = nu;
+      fetch(t + (int)blockDim.x);
+      const bool have = t < total;
+      const bool from_soa = have && t < tail0;
+      const bool is_new = have && !from_soa;
+      const uint32_t gi = (uint32_t)t;
+
+      // ---- common step: no boundary in either half step and a draw at or above
+      // x >= p, so certainly no event; identical arithmetic to the general path
+      bool slow = false;
+      if (from_soa && !(rfl & kDead)) {
+        const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
+        const LayCache c = load_lay(I, l, s);
+        const double mu = (double)rmu;
+        const double zm = (double)rz + (c.v * mu) * a.h;
+        const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
+                                 a.key1);
+        const double E_ev = (double)rE * 0x1p-30;
+        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
+        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+        const double ze = zm + (c.v * mu) * a.h;
+        slow = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        if (!slow) {
+          const double zs = to_store<F>(ze);
+          deposit<MODE>(a, I, s_dens, s_cur, s_edges, zs, mu, rE, rfl, c.v);
+          sp.z[gi] = (F)zs;
+          lc.dep += 1;
+        }
+      }
+      // ---- new primaries (source term, Eq. 17) take the general path at once
+      if (__ballot(is_new)) {
+        double z = 0.0, mu = 0.0;
+        uint32_t E = 0, fl = kDead, lo = 0;
+        if (is_new) {
+          const int64_t j = kk + S * (f0 + (t - tail0));
+          const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
+          const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
+          double z0;
+          if (I.src_lambda > 0.0)
+            z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
+          else
+            z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
+          z = to_store<F>(z0);
+          mu = to_store<F>(dircos(w.y));
+          const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
+          E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
+          int l = 0;
+          for (int q = 1; q < I.n_layers; ++q)
+            if (I.lay[q].x <= z) l = q;
+          fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift);
+          lo = root;
+        }
+        general(false, is_new, gi, z, mu, E, fl, lo, 0u, 0ull);
+        if (qn >= 64) drain_kids(64);
+      }
+      // ---- queue the general-path slots; each general pass adds at most 64 newborns,
+      // so the newborn queue (128) is drained below 64 before every pass
+      const uint64_t ms = __ballot(slow);
+      if (ms) {
+        if (slow) SQ[sn + prefix_count(ms)] = gi;
+        sn += __popcll(ms);
+      }
+      if (sn >= 64) {
+        drain_slow(64);
+        if (qn >= 64) drain_kids(64);
+      }
     }
+    while (sn > 0) {
+      drain_slow(sn < 64 ? sn : 64);
+      if (qn >= 64) drain_kids(64);
+    }
+    while (qn > 0) drain_kids(qn < 64 ? qn : 64);
     if (lc.dep) atomicAdd(&s_cnt[PIC_C_ALIVE], (unsigned long long)lc.dep);
     if (lc.tr) atomicAdd(&s_cnt[PIC_C_TRANSMIT], (unsigned long long)lc.tr);
     if (lc.ri) atomicAdd(&s_cnt[PIC_C_REFL_IF], (unsigned long long)lc.ri);
