@@ -42,22 +42,34 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def alg_bytes(cnt: np.ndarray, fp64: bool) -> np.ndarray:
+def alg_bytes(cnt: np.ndarray, fp64: bool, general=None, z_every: int = 1) -> np.ndarray:
     """Algorithmic HBM bytes of each step launch, from the step counters.
 
-    Per carrier alive at the start of the step: read z, cos(theta), E, uid, flags and
-    write z.  Per event: write cos(theta) and E.  Per boundary hit: write cos(theta)
+    Per carrier alive at the start of the step: read z, cos(theta), E, uid and flags.
+    z is written by every carrier on the last step of each z write-back period (z_every
+    steps, and the last step of the run) and otherwise only by the carriers that took
+    the general path (`general`, per step; all of them if unknown), which also write
+    their flags.  Per event: write cos(theta) and E.  Per boundary hit: write cos(theta)
     (reflection) or the flags (transmission).  Per absorbed carrier: write its flags.
-    Per appended carrier (new primary or secondary): write the whole state.
+    Per appended carrier (new primary or secondary): write the whole state.  Not
+    counted: the flags rewrite of a carrier whose write-back stamp is reset (a carrier
+    that took the general path earlier in the period).
     """
     sz = 8 if fp64 else 4
     state = 2 * sz + 4 + 8 + 4
-    alive_prev = np.concatenate([[0], cnt[:-1, 9]])
+    n = len(cnt)
+    alive_prev = np.concatenate([[0], cnt[:-1, 9]]).astype(np.float64)
+    gen = alive_prev if general is None else np.asarray(general, dtype=np.float64)
+    k = max(1, int(z_every))
+    idx = np.arange(n)
+    write = (idx % k == k - 1) | (idx == n - 1)
+    z_writes = np.where(write, alive_prev, gen)
+    stamp_writes = np.where(write, 0.0, gen)
     ev = cnt[:, 1] + cnt[:, 2]
     hits = cnt[:, 6] + cnt[:, 7] + cnt[:, 8]
     appended = cnt[:, 0] + cnt[:, 3]
-    return (alive_prev * (state + sz) + ev * (sz + 4) + hits * sz + cnt[:, 4] * 4
-            + appended * state).astype(np.float64)
+    return (alive_prev * state + z_writes * sz + stamp_writes * 4 + ev * (sz + 4) + hits * sz
+            + cnt[:, 4] * 4 + appended * state).astype(np.float64)
 
 
 def particle_steps(cnt: np.ndarray) -> int:
@@ -65,36 +77,18 @@ def particle_steps(cnt: np.ndarray) -> int:
     return int((alive_prev + cnt[:, 0]).sum())
 
 
-def kernel_timing(sim, prob):
-    """One extra run launched step by step with HIP events on the library's stream:
-    mean duration of the step-kernel launch and algorithmic bytes per launch."""
-    import torch
-
-    tune = sim.tuning()
-    every = tune["compact_every"]
-    sim.set_tuning(use_graph=0, compact_every=0)
+def kernel_timing(sim):
+    """One extra run launched step by step with HIP events that the library records on
+    its stream around each step launch and its compaction.  Returns rows (ms step launch,
+    ms compaction, carriers whose step took the common path, carriers that took the
+    general path) and the run's counters."""
     sim.reset()
-    st = sim.stream
-    mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    s_ev = [mk() for _ in range(prob.n_steps)]
-    e_ev = [mk() for _ in range(prob.n_steps)]
-    comp = []
-    for n in range(prob.n_steps):
-        s_ev[n].record(st)
-        sim.step(1)
-        e_ev[n].record(st)
-        if every and (n + 1) % every == 0 and n + 1 < prob.n_steps:
-            a, b = mk(), mk()
-            a.record(st)
-            sim.compact()
-            b.record(st)
-            comp.append((a, b))
-    st.synchronize()
-    ms = np.array([s_ev[n].elapsed_time(e_ev[n]) for n in range(prob.n_steps)])
-    comp_ms = float(sum(a.elapsed_time(b) for a, b in comp))
+    sim.time_kernels(True)
+    sim.step()
     cnt = sim.counters()
-    sim.set_tuning(use_graph=tune["use_graph"], compact_every=every)
-    return ms, cnt, comp_ms
+    rows = sim.kernel_times()
+    sim.time_kernels(False)
+    return rows, cnt
 
 
 def cpu_baseline(prob, roots: int):
@@ -364,22 +358,26 @@ def main():
     roof = None
     extra = {}
     if not args.no_kernel_timing:
-        ms, cnt2, comp_ms = kernel_timing(sim, prob)
+        rows, cnt2 = kernel_timing(sim)
         assert np.array_equal(cnt2, cnt), "step-by-step run differs from the graph run"
-        b = alg_bytes(cnt2, prob.state_fp64)
+        b = alg_bytes(cnt2, prob.state_fp64, general=rows[:, 3],
+                      z_every=sim.tuning()["z_every"])
+        ms, c_ms = rows[:, 0], rows[:, 1]
         achieved = b.sum() / (ms.sum() * 1e-3) / 1e9
         traffic = measured_traffic() if args.workload == "batched" else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic, 0))
-        extra["step_kernel"] = dict(launches=int(prob.n_steps),
+        left = float(rows[:, 3].sum() / max(1.0, rows[:, 2:4].sum()))
+        extra["step_kernel"] = dict(kernel="k_step", launches=int(len(rows)),
                                     mean_launch_ms=round(float(ms.mean()), 4),
                                     alg_bytes_per_launch=float(b.mean()),
                                     bytes_per_particle_step=round(float(b.sum() / ps), 2),
+                                    general_path_fraction=round(left, 5),
                                     kernel_source=kernel_source_hash(),
-                                    compaction_ms_per_run=round(comp_ms, 3))
-        print(f"[bench] step kernel: {ms.mean():.4f} ms/launch, {achieved:.1f} GB/s algorithmic",
-              file=sys.stderr, flush=True)
+                                    compaction_ms_per_run=round(float(c_ms.sum()), 3))
+        print(f"[bench] step kernel: {ms.mean():.4f} ms/launch, {achieved:.1f} GB/s algorithmic, "
+              f"general-path fraction {left:.4f}", file=sys.stderr, flush=True)
     extra["tuning"] = sim.tuning()
     sim.close()
     torch.cuda.empty_cache()

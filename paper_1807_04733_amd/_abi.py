@@ -26,7 +26,8 @@ STATUS = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ENOMEM", 3: "PIC_ECAPACITY", 4: 
 
 EXPORTS = ("pic_workspace_size", "pic_init", "pic_inject", "pic_step", "pic_compact", "pic_deposit",
            "pic_backward", "pic_counters", "pic_reset", "pic_set_tuning", "pic_get_tuning",
-           "pic_layout_of", "pic_autotune", "pic_destroy", "pic_last_error")
+           "pic_layout_of", "pic_autotune", "pic_time_kernels", "pic_kernel_times",
+           "pic_destroy", "pic_last_error")
 
 
 class PicInstance(C.Structure):
@@ -63,7 +64,7 @@ class PicConfig(C.Structure):
 
 class PicTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("grid", C.c_int32), ("compact_every", C.c_int32),
-                ("compact_frac", C.c_float), ("use_graph", C.c_int32)]
+                ("compact_frac", C.c_float), ("use_graph", C.c_int32), ("z_every", C.c_int32)]
 
 
 class PicLayout(C.Structure):
@@ -109,6 +110,8 @@ def load():
         "pic_get_tuning": ([vp, P(PicTuning)], C.c_int),
         "pic_layout_of": ([vp, P(PicLayout)], C.c_int),
         "pic_autotune": ([vp, C.c_int32, P(PicTuning)], C.c_int),
+        "pic_time_kernels": ([vp, C.c_int32], C.c_int),
+        "pic_kernel_times": ([vp, P(C.c_double), C.c_int32, P(C.c_int32)], C.c_int),
         "pic_destroy": ([vp], None),
         "pic_last_error": ([], C.c_char_p),
     }

@@ -1,6 +1,7 @@
 // Host side of the libpic C ABI: validation, workspace layout, table upload, the step
 // driver (direct launches or a captured hipGraph) and the integer-to-binary64 bins.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -49,6 +50,7 @@ struct Plan {
   int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
   int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
   int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
+  int64_t off_stats;
   int64_t off_grad = -1, off_S = -1, off_r = -1, off_R = -1;
   int K = 0;
   int64_t n_roots = 0;
@@ -193,6 +195,7 @@ Plan make_plan(const pic_config* c) {
   p.off_counters = take((int64_t)c->n_steps * kNC * 8);
   p.off_queue = take((int64_t)c->n_steps * 4 * 2);
   p.off_status = take(64);
+  p.off_stats = take((int64_t)c->n_steps * 2 * 8);
   if (c->adjoint) {
     const pic_instance& I0 = c->inst[0];
     p.K = I0.n_channels + I0.n_ttables * I0.t_entries;
@@ -229,12 +232,24 @@ struct pic_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   int g_start = -1, g_n = -1;
+  // per-launch timing: events before and after each step launch and after its compaction
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 3>> tev;
+  std::vector<int> tstep;
 
   template <typename T>
   T* at(int64_t off) const { return off < 0 ? nullptr : (T*)(ws + off); }
 };
 
 namespace {
+
+void drop_events(pic_ctx* c) {
+  for (auto& ev : c->tev)
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  c->tev.clear();
+  c->tstep.clear();
+}
 
 void drop_graph(pic_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -244,7 +259,8 @@ void drop_graph(pic_ctx* c) {
   c->g_start = c->g_n = -1;
 }
 
-// Dynamic LDS of one step launch (the layout k_step expects).
+// Dynamic LDS of one step launch: [density | current] histograms, then per wave a
+// newborn queue and a general-path slot queue.
 size_t lds_for(const pic_ctx* c, int block, bool dens_step) {
   const size_t dens = dens_step && c->dens_lds ? (size_t)c->lds_dens_words * 4 : 0;
   const size_t cur_at = (dens + 15) & ~(size_t)15;
@@ -293,6 +309,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.counters = c->at<int64_t>(p.off_counters);
   a.queue = c->at<int32_t>(p.off_queue);
   a.status = c->at<uint32_t>(p.off_status);
+  a.stats = c->at<unsigned long long>(p.off_stats);
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
   a.n_ebins = c->cfg.n_ebins;
@@ -315,6 +332,8 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.lds_dens_words = a.dens_on ? c->lds_dens_words : 0;
   a.lds_cur_words = c->lds_cur_words;
   a.inst_bytes = c->inst_bytes;
+  a.z_phase = 0;
+  a.z_write = 1;
   return a;
 }
 
@@ -343,15 +362,32 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
   const int n_slabs = (int)c->plan.slab_inst.size();
   int grid = c->tune.grid > 0 ? c->tune.grid : 512;
   grid = std::max(1, std::min(grid, n_slabs));
+  const int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
   for (int s = start; s < start + n; ++s) {
     StepArgs a = step_args(c, s);
-    const size_t lds = lds_for(c, c->tune.block, a.dens_on != 0);
-    HIP_TRY(launch_step(a, fp64, grid, c->tune.block, lds, c->stream));
+    a.z_phase = (s - start) % K;
+    a.z_write = (a.z_phase == K - 1 || s == start + n - 1) ? 1 : 0;
+    StepLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    L.grid = grid;
+    L.block = c->tune.block;
+    L.lds = lds_for(c, c->tune.block, a.dens_on != 0);
+    hipEvent_t* ev = nullptr;
+    if (c->timing) {
+      c->tev.emplace_back();
+      c->tstep.push_back(s);
+      ev = c->tev.back().data();
+      for (int k = 0; k < 3; ++k) ev[k] = nullptr;
+      for (int k = 0; k < 3; ++k) HIP_TRY(hipEventCreate(&ev[k]));
+      for (int k = 0; k < 2; ++k) L.ev[k] = ev[k];
+    }
+    HIP_TRY(launch_step(a, fp64, L, c->stream));
     if (c->tune.compact_every > 0 && !c->plan.debug && (s + 1) % c->tune.compact_every == 0 &&
         s + 1 < c->cfg.n_steps) {
       CompactArgs ca = compact_args(c);
       HIP_TRY(launch_compact(ca, fp64, c->tune.block, c->stream));
     }
+    if (ev) HIP_TRY(hipEventRecord(ev[2], c->stream));
   }
   return PIC_OK;
 }
@@ -432,6 +468,7 @@ pic_status clear_state(pic_ctx* c) {
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_counters), (int64_t)c->cfg.n_steps * kNC * 2, 0, c->stream));
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_queue), (int64_t)c->cfg.n_steps * 2, 0, c->stream));
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_status), 16, 0, c->stream));
+  HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_stats), (int64_t)c->cfg.n_steps * 4, 0, c->stream));
   c->step = 0;
   return PIC_OK;
 }
@@ -471,6 +508,7 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
   c->tune.compact_every = 8;
   c->tune.compact_frac = 0.15f;
   c->tune.use_graph = 1;
+  c->tune.z_every = 4;
   // LDS per workgroup: the density slice and the current slice of the largest instance,
   // plus one newborn queue per wave.  The density histogram goes to LDS when it fits
   // next to the queues of a 256-thread block; otherwise density uses global atomics.
@@ -529,7 +567,7 @@ pic_status pic_step(pic_ctx* c, int32_t n) {
   if (n < 0 || c->step + n > c->cfg.n_steps) return fail(PIC_EINVAL, "step count beyond n_steps");
   if (n == 0) return PIC_OK;
   const int start = c->step;
-  if (c->tune.use_graph && n > 1) {
+  if (c->tune.use_graph && n > 1 && !c->timing) {
     if (!(c->gexec && c->g_start == start && c->g_n == n)) {
       drop_graph(c);
       HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -596,6 +634,7 @@ pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (!(b == 64 || b == 128 || b == 256 || b == 512)) return fail(PIC_EINVAL, "block must be 64, 128, 256 or 512");
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
+  if (t->z_every < 1 || t->z_every > kMaxZEvery) return fail(PIC_EINVAL, "z_every must be 1..8");
   if (lds_for(c, b, true) > c->max_lds)
     return fail(PIC_EINVAL, "block too large for the LDS histograms of this configuration");
   c->tune = *t;
@@ -810,6 +849,18 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
       }
     }
   }
+  // stage 3: write-back period of z on the common path
+  for (int k : {1, 2, 4, 8}) {
+    pic_tuning t = win;
+    t.z_every = k;
+    float ms = 0;
+    pic_status st = time_trial(c, t, steps, &ms);
+    if (st != PIC_OK) return st;
+    if (ms < best_ms) {
+      best_ms = ms;
+      win = t;
+    }
+  }
   win.use_graph = 1;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -821,10 +872,47 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   return clear_state(c);
 }
 
+pic_status pic_time_kernels(pic_ctx* c, int32_t enable) {
+  if (!c) return fail(PIC_EINVAL, "null context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_events(c);
+  c->timing = enable != 0;
+  return PIC_OK;
+}
+
+pic_status pic_kernel_times(pic_ctx* c, double* out, int32_t max_steps, int32_t* n_out) {
+  if (!c || !n_out || (max_steps > 0 && !out)) return fail(PIC_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!out) {  // count only; the events stay
+    *n_out = (int32_t)c->tev.size();
+    return PIC_OK;
+  }
+  std::vector<unsigned long long> stats((size_t)c->cfg.n_steps * 2);
+  HIP_TRY(hipMemcpy(stats.data(), c->at<void>(c->plan.off_stats), stats.size() * 8,
+                    hipMemcpyDeviceToHost));
+  const int n = std::min<int>((int)c->tev.size(), std::max(0, max_steps));
+  for (int k = 0; k < n; ++k) {
+    const auto& ev = c->tev[k];
+    float f = 0, m = 0;
+    HIP_TRY(hipEventElapsedTime(&f, ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&m, ev[1], ev[2]));
+    const int s = c->tstep[k];
+    double* o = out + (size_t)k * 4;
+    o[0] = f;
+    o[1] = m;
+    o[2] = (double)stats[(size_t)s * 2];
+    o[3] = (double)stats[(size_t)s * 2 + 1];
+  }
+  *n_out = (int32_t)c->tev.size();
+  drop_events(c);
+  return PIC_OK;
+}
+
 void pic_destroy(pic_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
+  drop_events(c);
   delete c;
 }
 

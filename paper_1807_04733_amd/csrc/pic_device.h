@@ -150,6 +150,17 @@ __device__ __forceinline__ LayCache load_lay(const DevInst& I, int l, int s) {
   return LayCache{I.lay[l].x, I.lay[l].y, C.x, C.y};
 }
 
+// n straight flights of a whole step each, from a stored position: the common-path step
+// (two half-step additions in binary64, then the storage rounding) repeated exactly.
+template <typename F>
+__device__ __forceinline__ double replay_flights(double z, double vmh, int n) {
+  for (int k = 0; k < n; ++k) {
+    const double zm = z + vmh;
+    z = to_store<F>(zm + vmh);
+  }
+  return z;
+}
+
 // Transport half step with the layer's table values cached (same arithmetic and draws
 // as half_push).
 __device__ __forceinline__ void half_push_c(const DevInst& I, LayCache& c, double& z, double& mu,

@@ -29,6 +29,11 @@ constexpr uint32_t kLayerMask = 0xFu;
 constexpr int kGenShift = 8;
 constexpr uint32_t kGenMask = 0xFFu;
 constexpr uint32_t kDead = 0x80000000u;
+// Steps since the stored z was written, counted from the last write-back boundary (see
+// StepArgs::z_phase); 0 outside a pic_step call.
+constexpr int kStampShift = 5;
+constexpr uint32_t kStampMask = 0x7u;
+constexpr int kMaxZEvery = 8;
 
 // Device status bits.
 constexpr uint32_t kStOverflow = 1u;
@@ -76,6 +81,7 @@ struct StepArgs {
   int64_t* counters;           // [n_steps][kNC]
   int32_t* queue;              // [n_steps] slab dispenser
   uint32_t* status;
+  unsigned long long* stats;   // [n_steps][2] carriers finished by the common step / left
   int32_t n_slabs, n_inst, n_ebins, n_steps;
   int32_t step;
   uint32_t key0, key1;
@@ -88,6 +94,11 @@ struct StepArgs {
   int32_t lds_dens_words;      // u32 words of the LDS density histogram
   int32_t lds_cur_words;       // u64 words of the LDS current histogram
   int32_t inst_bytes;          // bytes of DevInst copied into LDS
+  // Write-back schedule of z on the common path: the stored z of a carrier is its
+  // position at the start of step (this step - z_phase + stamp); the steps in between
+  // were straight flights and are recomputed.  z_write: this step stores z and clears
+  // the stamps (the last step of a write-back period or of a pic_step call).
+  int32_t z_phase, z_write;
 };
 
 struct AdjArgs {
@@ -122,9 +133,15 @@ struct CompactArgs {
 constexpr size_t kChildQueueBytes = 128 * (8 + 4 * 4);
 constexpr size_t kSlowQueueBytes = 128 * 4;
 
+// Launch shape of one step.
+struct StepLaunch {
+  int grid, block;
+  size_t lds;                  // dynamic LDS (histograms + per-wave queues)
+  hipEvent_t ev[2];            // optional: recorded before and after the launch
+};
+
 // launchers (pic_kernels.hip)
-hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
-                       hipStream_t s);
+hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& A, bool fp64, int adj, int grid, int block,
                           hipStream_t s);

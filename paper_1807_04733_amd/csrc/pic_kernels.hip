@@ -142,7 +142,8 @@ __device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst&
       lin = sw.w | 1u;
       if (lin == phi) lin ^= 2u;
     }
-    uint32_t cfl = cs | (pfl & ~kSpinMask);
+    const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
+    uint32_t cfl = cs | (pfl & ~kSpinMask) | (z_next << kStampShift);
     HitCounts h{0, 0, 0};
     LayCache cc = load_lay(I, l, (int)cs);
     half_push_c(I, cc, cz, cmu, cfl, cE, lo, lin, (uint32_t)a.step, kTagHalf2, a.h, a.key0,
@@ -194,10 +195,16 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   __shared__ unsigned long long s_cnt[kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
   __shared__ int s_slab, s_app, s_dead;
+  __shared__ unsigned long long s_fast, s_left;
 
   const int tid = threadIdx.x;
   const int lane = __lane_id();
   const int wave = tid >> 6;
+  if (tid == 0) {
+    s_fast = 0;
+    s_left = 0;
+  }
+  uint32_t n_fast = 0, n_left = 0;
   for (int i = tid; i < a.lds_dens_words; i += blockDim.x) s_dens[i] = 0;
   for (int i = tid; i < a.lds_cur_words; i += blockDim.x) s_cur[i] = 0;
   for (int i = tid; i < a.n_ebins; i += blockDim.x) s_edges[i] = a.e_edges[i];
@@ -206,6 +213,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   F* gz = (F*)a.z;
   F* gmu = (F*)a.mu;
   const uint32_t step = (uint32_t)a.step;
+  // stamp of every z this step stores (0 when the step ends a write-back period)
+  const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
   ChildQueue& Q = s_q[wave];
   uint32_t* SQ = s_slow + wave * kSlowQ;
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
@@ -324,6 +333,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           z = to_store<F>(z);
           fl |= kDead;
         }
+        // z is stored below: the stamp says at which step of the write-back period
+        fl = (fl & ~(kStampMask << kStampShift)) | (died ? 0u : z_next << kStampShift);
         if (mu != mu_in) dirty |= 1u;
         if (fl != fl_in) dirty |= 4u;
         if (DEBUG) evp += ((uint64_t)hc.tr << 16) + ((uint64_t)(hc.ri + hc.rs) << 32);
@@ -402,6 +413,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
         if (DEBUG) evp = sp.ev[g];
+        const int d = a.z_phase - (int)((fl >> kStampShift) & kStampMask);
+        if (d > 0) {
+          const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
+          z = replay_flights<F>(z, (c.v * mu) * a.h, d);
+        }
       }
       general(act, false, g, z, mu, E, fl, lo, hi, evp);
       wave_sync();
@@ -451,7 +467,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
         const LayCache c = load_lay(I, l, s);
         const double mu = (double)rmu;
-        const double zm = (double)rz + (c.v * mu) * a.h;
+        const uint32_t st = (rfl >> kStampShift) & kStampMask;
+        const double z0 = replay_flights<F>((double)rz, (c.v * mu) * a.h, a.z_phase - (int)st);
+        const double zm = z0 + (c.v * mu) * a.h;
         const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
                                  a.key1);
         const double E_ev = (double)rE * 0x1p-30;
@@ -462,8 +480,14 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         if (!slow) {
           const double zs = to_store<F>(ze);
           deposit<MODE>(a, I, s_dens, s_cur, s_edges, zs, mu, rE, rfl, c.v);
-          sp.z[gi] = (F)zs;
+          if (a.z_write) {
+            sp.z[gi] = (F)zs;
+            if (st) sp.fl[gi] = rfl & ~(kStampMask << kStampShift);
+          }
           lc.dep += 1;
+          n_fast += 1;
+        } else {
+          n_left += 1;
         }
       }
       // ---- new primaries (source term, Eq. 17) take the general path at once
@@ -523,9 +547,15 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   }
   if (cur_inst >= 0) flush_bins<MODE>(a, s_inst, s_dens, s_cur);
   if (bad) atomicOr(a.status, kStHits);
+  if (n_fast) atomicAdd(&s_fast, (unsigned long long)n_fast);
+  if (n_left) atomicAdd(&s_left, (unsigned long long)n_left);
   __syncthreads();
   if (tid < kNC && s_cnt[tid])
     atomicAdd((unsigned long long*)&a.counters[(int64_t)a.step * kNC + tid], s_cnt[tid]);
+  if (tid == 0) {
+    if (s_fast) atomicAdd(&a.stats[(int64_t)a.step * 2 + 0], s_fast);
+    if (s_left) atomicAdd(&a.stats[(int64_t)a.step * 2 + 1], s_left);
+  }
 }
 
 // In-place compaction of slabs whose tombstones exceed a fraction of their tail.  One
@@ -618,17 +648,18 @@ __global__ void k_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, 
 }
 
 template <typename F, int MODE>
-static void launch_mode(const StepArgs& a, int grid, int block, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_step<F, MODE>), dim3(grid), dim3(block), lds, s, a);
+static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
+  if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
+  hipLaunchKernelGGL((k_step<F, MODE>), dim3(L.grid), dim3(L.block), L.lds, s, a);
+  if (L.ev[1]) (void)hipEventRecord(L.ev[1], s);
 }
 
 template <typename F>
-static hipError_t launch_prec(const StepArgs& a, int mode, int grid, int block, size_t lds,
-                              hipStream_t s) {
+static hipError_t launch_prec(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s) {
   switch (mode) {
 #define PIC_MODE(m) \
   case m:           \
-    launch_mode<F, m>(a, grid, block, lds, s); \
+    launch_mode<F, m>(a, L, s); \
     break;
     PIC_MODE(0) PIC_MODE(1) PIC_MODE(2) PIC_MODE(3) PIC_MODE(4) PIC_MODE(5)
     PIC_MODE(8) PIC_MODE(9) PIC_MODE(10) PIC_MODE(11) PIC_MODE(12) PIC_MODE(13)
@@ -663,13 +694,11 @@ hipError_t set_step_lds_limit(size_t bytes) {
   return e;
 }
 
-hipError_t launch_step(const StepArgs& a, bool fp64, int grid, int block, size_t lds,
-                       hipStream_t s) {
+hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const int mode = (a.debug ? kModeDebug : 0) |
                    (a.dens_on ? (a.dens_lds ? kModeDensLds : kModeDensGlobal) : 0) |
                    (a.cur_on ? kModeCur : 0);
-  return fp64 ? launch_prec<double>(a, mode, grid, block, lds, s)
-              : launch_prec<float>(a, mode, grid, block, lds, s);
+  return fp64 ? launch_prec<double>(a, mode, L, s) : launch_prec<float>(a, mode, L, s);
 }
 
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s) {

@@ -154,6 +154,21 @@ class PicSim:
         _abi.check(self.lib.pic_autotune(self.handle, int(trial_steps), C.byref(t)))
         return {k: getattr(t, k) for k, _ in t._fields_}
 
+    def time_kernels(self, enable: bool = True) -> None:
+        """Record HIP events around each step launch and its compaction on the following
+        steps (launched directly, no graph)."""
+        _abi.check(self.lib.pic_time_kernels(self.handle, 1 if enable else 0))
+
+    def kernel_times(self) -> np.ndarray:
+        """Rows (ms of the step launch, ms of the compaction after it, carriers whose step
+        took the common path, carriers that took the general path) of the timed steps."""
+        n = C.c_int32(0)
+        _abi.check(self.lib.pic_kernel_times(self.handle, None, 0, C.byref(n)))
+        out = np.zeros((max(n.value, 1), 4), dtype=np.float64)
+        _abi.check(self.lib.pic_kernel_times(
+            self.handle, out.ctypes.data_as(C.POINTER(C.c_double)), n.value, C.byref(n)))
+        return out[:n.value]
+
     @property
     def n_params(self) -> int:
         it = self.problem.instances[0]

@@ -122,14 +122,17 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
     prob = W.config1(parallel=True, n_primaries=6000, n_steps=120)
     prob.dens_stride = 3
     ref = oracle_mod.run(prob)
-    for tuning in ({"block": 64, "grid": 7, "compact_every": 0},
-                   {"block": 128, "grid": 1000, "compact_every": 1, "compact_frac": 0.0},
-                   {"block": 256, "grid": 64, "compact_every": 5, "use_graph": 0}):
+    for tuning in ({"block": 64, "grid": 7, "compact_every": 0, "z_every": 1},
+                   {"block": 128, "grid": 1000, "compact_every": 1, "compact_frac": 0.0,
+                    "z_every": 8},
+                   {"block": 256, "grid": 64, "compact_every": 5, "use_graph": 0, "z_every": 3},
+                   {"block": 512, "grid": 300, "compact_every": 3, "z_every": 5}):
         from paper_1807_04733_amd import PicSim
         _say(f"[parity] launch shape {tuning}")
         sim = PicSim(prob, slab_primaries=1000, tuning=tuning)
-        sim.step(50)
-        sim.step(70)
+        # calls of uneven length: z is written back at the end of each call
+        for n in (50, 1, 6, 63):
+            sim.step(n)
         dens, cur = sim.int_bins()
         cnt = sim.counters()
         sim.close()
