@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batched", choices=["batched", "valve", "bilayer"])
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-roots", type=int, default=300)
+    ap.add_argument("--cpu-roots", type=int, default=3000)
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON dict of launch tuning")
     ap.add_argument("--slab", type=int, default=0)

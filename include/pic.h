@@ -22,8 +22,9 @@
  *     workspace of at least pic_workspace_size() bytes (256-byte aligned) and keeps it
  *     alive until pic_destroy().  Output arrays passed to pic_deposit() are caller-owned
  *     device memory.  All device work is enqueued on the HIP stream given to pic_init()
- *     (NULL = the default stream); only pic_counters(), pic_autotune() and pic_destroy()
- *     synchronize.
+ *     (NULL = the default stream).  pic_init(), pic_inject(), pic_counters(),
+ *     pic_backward(), pic_autotune(), pic_time_kernels(), pic_kernel_times() and
+ *     pic_destroy() wait for that stream; the other calls only enqueue work.
  *   - A context is not thread-safe; distinct contexts may be used concurrently on
  *     distinct streams.
  *
@@ -203,9 +204,10 @@ pic_status pic_set_tuning(pic_ctx* ctx, const pic_tuning* t);
 pic_status pic_get_tuning(const pic_ctx* ctx, pic_tuning* t);
 pic_status pic_layout_of(const pic_ctx* ctx, pic_layout* out);
 
-/* Time candidate launch shapes on the first `trial_steps` steps of this context's run
- * and store the fastest in the context (and in a per-device cache keyed by the config
- * signature).  Resets the context before and after.  Synchronizes. */
+/* Time candidate tunings and store the fastest in the context (and in a per-device cache
+ * keyed by the config signature): workgroup size and grid on the first `trial_steps`
+ * steps of this context's run, then the compaction cadence and the z write-back period
+ * on the first 4 x trial_steps.  Resets the context before and after.  Synchronizes. */
 pic_status pic_autotune(pic_ctx* ctx, int32_t trial_steps, pic_tuning* best);
 
 /* Per-launch timing, for measurement.  pic_time_kernels(ctx, 1) makes the following

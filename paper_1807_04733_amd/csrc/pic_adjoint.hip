@@ -28,6 +28,7 @@
 
 namespace pic {
 
+constexpr int kSlowQ = (int)(kSlowQueueBytes / 4);  // general-path slots per wave queue
 constexpr int kNfShift = 16;
 constexpr uint32_t kNfMask = 0x7FFFu;
 
@@ -174,8 +175,11 @@ __device__ __forceinline__ int append_slot(bool want, int* s_app, int tail0) {
 template <typename F, int ADJ>
 __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
   const StepArgs& a = A.s;
-  // this step's slice of dL/d(current) for the workgroup's instance (dynamic LDS)
+  // dynamic LDS: this step's slice of dL/d(current) for the workgroup's instance, then
+  // one general-path slot queue per wave
   extern __shared__ double s_gcur[];
+  uint32_t* s_slow =
+      (uint32_t*)((unsigned char*)s_gcur + (((size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15));
   __shared__ DevInst s_inst;
   __shared__ double s_grad[kMaxK];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
@@ -186,6 +190,9 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
   F* gz = (F*)a.z;
   F* gmu = (F*)a.mu;
   const uint32_t step = (uint32_t)a.step;
+  // stamp of every z this step stores (0 when the step ends a write-back period)
+  const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
+  uint32_t* SQ = s_slow + wave * kSlowQ;
   const AdjOps<ADJ> ops{A, s_grad};
   int cur_inst = -1;
   bool bad = false;
@@ -223,76 +230,13 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
     const int64_t f0 = count_mod(cum[step], kk, S);
     const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
     const int total = tail0 + n_inj;
+    int sn = 0;  // wave-uniform fill of this wave's general-path queue
 
-    // next slot of this lane, fetched one iteration ahead (as in the forward step)
-    F nz = 0, nmu = 0;
-    uint32_t nE = 0, nfl = kDead;
-    uint64_t nu = 0;
-    auto fetch = [&](int t) {
-      if (t < tail0) {
-        const int64_t g = base + t;
-        nfl = a.flags[g];
-        nz = gz[g];
-        nmu = gmu[g];
-        nE = a.E[g];
-        nu = a.uid[g];
-      } else {
-        nfl = kDead;
-      }
-    };
-    fetch(wave * 64 + lane);
-    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
-      const int t = tb + lane;
-      const F rz = nz, rmu = nmu;
-      const uint32_t rE = nE, rfl = nfl;
-      const uint64_t ru = nu;
-      fetch(t + (int)blockDim.x);
-      const bool have = t < total;
-      const bool from_soa = have && t < tail0;
-      const bool is_new = have && !from_soa;
-      // new primaries take their slot first, so that their score row exists
-      const int newpos = append_slot(is_new, &s_app, tail0);
-      int64_t gi = base + t;
-      bool room = true;
-      if (is_new) {
-        room = newpos < cap;
-        gi = base + newpos;
-        if (!room) atomicOr(a.status, kStOverflow);
-      }
-      double z = 0.0, mu = 0.0;
-      uint32_t E = 0, fl = kDead, lo = 0, hi = 0;
-      if (from_soa) {
-        fl = rfl;
-        if (!(fl & kDead)) {
-          z = (double)rz;
-          mu = (double)rmu;
-          E = rE;
-          lo = (uint32_t)ru;
-          hi = (uint32_t)(ru >> 32);
-        }
-      } else if (is_new && room) {
-        const int64_t j = kk + S * (f0 + (t - tail0));
-        const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
-        const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
-        double z0;
-        if (I.src_lambda > 0.0)
-          z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
-        else
-          z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
-        z = to_store<F>(z0);
-        mu = to_store<F>(dircos(w.y));
-        const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
-        E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
-        int l = 0;
-        for (int q = 1; q < I.n_layers; ++q)
-          if (I.lay[q].x <= z) l = q;
-        fl = with_nf(s | ((uint32_t)l << kLayerShift) | (1u << kGenShift), step);
-        lo = root;
-        hi = 0;
-        if (ADJ == 1)
-          for (int k = 0; k < A.K; ++k) A.S[gi * A.K + k] = 0.0;
-        if (ADJ == 2) A.r[gi] = 0.0;
-      }
+    // ---------------------------------------------------------------- general path
+    // The whole replayed step of one carrier with its score terms.  All lanes of the wave
+    // call it together; lanes with nothing to do pass a dead carrier.
+    auto general = [&](bool is_new, int64_t gi, double z, double mu, uint32_t E, uint32_t fl,
+                       uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
       const bool alive0 = !(fl & kDead);
       bool died = false;
       AdjLane L{gi, lo, 0.0, false};
@@ -347,7 +291,8 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
                 }
                 uint32_t gen = (fl >> kGenShift) & kGenMask;
                 gen = gen < 255u ? gen + 1u : 255u;
-                uint32_t cfl = with_nf(cs | ((uint32_t)l << kLayerShift) | (gen << kGenShift),
+                uint32_t cfl = with_nf(cs | ((uint32_t)l << kLayerShift) | (gen << kGenShift) |
+                                           (z_next << kStampShift),
                                        step + 1);
                 if (ADJ == 1)
                   for (int k = 0; k < A.K; ++k) A.S[cg * A.K + k] = A.S[gi * A.K + k];
@@ -390,6 +335,8 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
             if (r != 0.0) atomicAdd(&A.R[lo], r);
           }
         }
+        // z is stored below: the stamp says at which step of the write-back period
+        fl = (fl & ~(kStampMask << kStampShift)) | (died ? 0u : z_next << kStampShift);
         if (is_new) {
           gz[gi] = (F)z;
           gmu[gi] = (F)mu;
@@ -405,7 +352,143 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
+    };
+
+    auto wave_sync = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // finish the top n queued general-path slots (state re-read from HBM)
+    auto drain_slow = [&](int n) {
+      wave_sync();
+      const bool act = lane < n;
+      const uint32_t t = act ? SQ[sn - n + lane] : 0u;
+      sn -= n;
+      const int64_t g = base + t;
+      uint32_t fl = kDead, E = 0, lo = 0, hi = 0;
+      double z = 0.0, mu = 0.0;
+      if (act) {
+        fl = a.flags[g];
+        z = (double)gz[g];
+        mu = (double)gmu[g];
+        E = a.E[g];
+        const uint64_t u = a.uid[g];
+        lo = (uint32_t)u;
+        hi = (uint32_t)(u >> 32);
+        const int d = a.z_phase - (int)((fl >> kStampShift) & kStampMask);
+        if (d > 0) {
+          const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
+          z = replay_flights<F>(z, (c.v * mu) * a.h, d);
+        }
+      }
+      general(false, g, z, mu, E, fl, lo, hi);
+      wave_sync();
+    };
+
+    // next slot of this lane, fetched one iteration ahead (as in the forward step)
+    F nz = 0, nmu = 0;
+    uint32_t nE = 0, nfl = kDead;
+    uint64_t nu = 0;
+    auto fetch = [&](int t) {
+      if (t < tail0) {
+        const int64_t g = base + t;
+        nfl = a.flags[g];
+        nz = gz[g];
+        nmu = gmu[g];
+        nE = a.E[g];
+        nu = a.uid[g];
+      } else {
+        nfl = kDead;
+      }
+    };
+    fetch(wave * 64 + lane);
+    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
+      const int t = tb + lane;
+      const F rz = nz, rmu = nmu;
+      const uint32_t rE = nE, rfl = nfl;
+      const uint64_t ru = nu;
+      fetch(t + (int)blockDim.x);
+      const bool have = t < total;
+      const bool from_soa = have && t < tail0;
+      const bool is_new = have && !from_soa;
+
+      // ---- common step: no boundary in either half step, a draw at or above x >= p
+      // (certainly no event) and, for the causal estimator, a deposit weight of 0: no
+      // score term at all; identical arithmetic to the general path
+      bool slow = false;
+      if (from_soa && !(rfl & kDead)) {
+        const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
+        const LayCache c = load_lay(I, l, s);
+        const double mu = (double)rmu;
+        const uint32_t st = (rfl >> kStampShift) & kStampMask;
+        const double z0 = replay_flights<F>((double)rz, (c.v * mu) * a.h, a.z_phase - (int)st);
+        const double zm = z0 + (c.v * mu) * a.h;
+        const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
+                                 a.key1);
+        const double E_ev = (double)rE * 0x1p-30;
+        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
+        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+        const double ze = zm + (c.v * mu) * a.h;
+        slow = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        if (!slow) {
+          const double zs = to_store<F>(ze);
+          const int64_t gi = base + t;
+          if (ADJ != 3) {
+            const double g = deposit_weight(A, I, zs, mu, rE, rfl, s_edges, s_gcur);
+            if (ADJ == 1 && g != 0.0) slow = true;
+            if (ADJ == 2 && g != 0.0) A.r[gi] += g;
+          }
+          if (!slow && a.z_write) {
+            gz[gi] = (F)zs;
+            if (st) a.flags[gi] = rfl & ~(kStampMask << kStampShift);
+          }
+        }
+      }
+      // ---- new primaries take their slot first, so that their score row exists
+      if (__ballot(is_new)) {
+        const int newpos = append_slot(is_new, &s_app, tail0);
+        int64_t gi = base + t;
+        double z = 0.0, mu = 0.0;
+        uint32_t E = 0, fl = kDead, lo = 0;
+        if (is_new) {
+          gi = base + newpos;
+          if (newpos >= cap) {
+            atomicOr(a.status, kStOverflow);
+          } else {
+            const int64_t j = kk + S * (f0 + (t - tail0));
+            const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
+            const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
+            double z0;
+            if (I.src_lambda > 0.0)
+              z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
+            else
+              z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
+            z = to_store<F>(z0);
+            mu = to_store<F>(dircos(w.y));
+            const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
+            E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
+            int l = 0;
+            for (int q = 1; q < I.n_layers; ++q)
+              if (I.lay[q].x <= z) l = q;
+            fl = with_nf(s | ((uint32_t)l << kLayerShift) | (1u << kGenShift), step);
+            lo = root;
+            if (ADJ == 1)
+              for (int k = 0; k < A.K; ++k) A.S[gi * A.K + k] = 0.0;
+            if (ADJ == 2) A.r[gi] = 0.0;
+          }
+        }
+        general(is_new && newpos < cap, gi, z, mu, E, fl, lo, 0u);
+      }
+      // ---- queue the general-path slots
+      const uint64_t ms = __ballot(slow);
+      if (ms) {
+        if (slow) SQ[sn + prefix_count(ms)] = (uint32_t)t;
+        sn += __popcll(ms);
+      }
+      if (sn >= 64) drain_slow(64);
     }
+    while (sn > 0) drain_slow(sn < 64 ? sn : 64);
     __syncthreads();
     if (tid == 0) {
       int nt = tail0 + s_app;
@@ -463,7 +546,8 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs A, uint32_t n_steps) 
 
 template <typename F>
 static hipError_t launch_adj_prec(const AdjArgs& A, int adj, int grid, int block, hipStream_t s) {
-  const size_t lds = (size_t)A.s.lds_cur_words * 8;
+  const size_t lds = (((size_t)A.s.lds_cur_words * 8 + 15) & ~(size_t)15) +
+                     (size_t)(block / 64) * kSlowQueueBytes;
   switch (adj) {
     case 1: hipLaunchKernelGGL((k_adj<F, 1>), dim3(grid), dim3(block), lds, s, A); break;
     case 2: hipLaunchKernelGGL((k_adj<F, 2>), dim3(grid), dim3(block), lds, s, A); break;

@@ -712,8 +712,11 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
   ca.S = adj == 1 ? A.S : nullptr;
   ca.K = adj == 1 ? p.K : 0;
   ca.r = adj == 2 ? A.r : nullptr;
+  const int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
   for (int n = 0; n < c->cfg.n_steps; ++n) {
     A.s = step_args(c, n);
+    A.s.z_phase = n % K;
+    A.s.z_write = (A.s.z_phase == K - 1 || n == c->cfg.n_steps - 1) ? 1 : 0;
     HIP_TRY(launch_adjoint(A, fp64, adj, grid, block, c->stream));
     // carriers move with their score rows (causal) or partial returns (tree pass 1)
     if (c->tune.compact_every > 0 && (n + 1) % c->tune.compact_every == 0 &&
@@ -833,6 +836,13 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
       }
     }
   }
+  // Stages 2 and 3 time longer prefixes: dead slots accumulate over the run, so the
+  // compaction cadence and the write-back period show their effect only later.
+  const int steps2 = std::min(c->cfg.n_steps, 4 * steps);
+  {
+    pic_status st = time_trial(c, win, steps2, &best_ms);
+    if (st != PIC_OK) return st;
+  }
   // stage 2: compaction cadence and threshold
   for (int every : {4, 8, 16, 0}) {
     for (float frac : {0.1f, 0.25f}) {
@@ -841,7 +851,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
       t.compact_every = every;
       t.compact_frac = frac;
       float ms = 0;
-      pic_status st = time_trial(c, t, steps, &ms);
+      pic_status st = time_trial(c, t, steps2, &ms);
       if (st != PIC_OK) return st;
       if (ms < best_ms) {
         best_ms = ms;
@@ -854,7 +864,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
     pic_tuning t = win;
     t.z_every = k;
     float ms = 0;
-    pic_status st = time_trial(c, t, steps, &ms);
+    pic_status st = time_trial(c, t, steps2, &ms);
     if (st != PIC_OK) return st;
     if (ms < best_ms) {
       best_ms = ms;
