@@ -42,34 +42,47 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def alg_bytes(cnt: np.ndarray, fp64: bool, general=None, z_every: int = 1) -> np.ndarray:
-    """Algorithmic HBM bytes of each step launch, from the step counters.
+def alg_bytes(cnt: np.ndarray, fp64: bool, launches=None, z_every: int = 1,
+              sub_steps: int = 1) -> np.ndarray:
+    """Algorithmic HBM bytes of each step-kernel launch, from the step counters.
 
-    Per carrier alive at the start of the step: read z, cos(theta), E, uid and flags.
-    z is written by every carrier on the last step of each z write-back period (z_every
-    steps, and the last step of the run) and otherwise only by the carriers that took
-    the general path (`general`, per step; all of them if unknown), which also write
-    their flags.  Per event: write cos(theta) and E.  Per boundary hit: write cos(theta)
-    (reflection) or the flags (transmission).  Per absorbed carrier: write its flags.
-    Per appended carrier (new primary or secondary): write the whole state.  Not
-    counted: the flags rewrite of a carrier whose write-back stamp is reset (a carrier
-    that took the general path earlier in the period).
+    `launches`: rows (..., carrier-steps on the general path, first step, number of
+    steps) of the timed launches; one launch per step when None.  Per launch: the state
+    (z, cos(theta), E, uid, flags) of every carrier alive at its start is read once.  z is
+    written by every carrier alive at the end of a launch that ends a z write-back period
+    (or the run), and once per general-path carrier-step, which also writes the flags in
+    launches that do not end a period.  Per event: cos(theta) and E.  Per boundary hit:
+    cos(theta) (reflection) or the flags (transmission).  Per absorbed carrier: its flags.
+    Per appended carrier (new primary or secondary): the whole state.  Not counted: the
+    flags rewrite that resets a write-back stamp, and the general path re-reading the
+    state of the carriers it takes (from L2 in the common case).
     """
     sz = 8 if fp64 else 4
     state = 2 * sz + 4 + 8 + 4
     n = len(cnt)
-    alive_prev = np.concatenate([[0], cnt[:-1, 9]]).astype(np.float64)
-    gen = alive_prev if general is None else np.asarray(general, dtype=np.float64)
-    k = max(1, int(z_every))
-    idx = np.arange(n)
-    write = (idx % k == k - 1) | (idx == n - 1)
-    z_writes = np.where(write, alive_prev, gen)
-    stamp_writes = np.where(write, 0.0, gen)
-    ev = cnt[:, 1] + cnt[:, 2]
-    hits = cnt[:, 6] + cnt[:, 7] + cnt[:, 8]
-    appended = cnt[:, 0] + cnt[:, 3]
-    return (alive_prev * state + z_writes * sz + stamp_writes * 4 + ev * (sz + 4) + hits * sz
-            + cnt[:, 4] * 4 + appended * state).astype(np.float64)
+    if launches is None:
+        launches = np.stack([np.zeros(n), np.zeros(n), np.zeros(n), cnt[:, 9],
+                             np.arange(n), np.ones(n)], axis=1)
+    t = max(1, int(sub_steps))
+    k = max(1, min(int(z_every), 8))
+    k = min(8 // t * t, (k + t - 1) // t * t)
+    alive = cnt[:, 9].astype(np.float64)
+    ev = (cnt[:, 1] + cnt[:, 2]).astype(np.float64)
+    hits = (cnt[:, 6] + cnt[:, 7] + cnt[:, 8]).astype(np.float64)
+    appended = (cnt[:, 0] + cnt[:, 3]).astype(np.float64)
+    out = []
+    for row in launches:
+        s0, m = int(row[4]), int(row[5])
+        last = s0 + m - 1
+        gen = float(row[3])
+        ap = alive[s0 - 1] if s0 > 0 else 0.0
+        write = (last % k == k - 1) or last == n - 1
+        sl = slice(s0, last + 1)
+        b = (ap * state + (alive[last] if write else 0.0) * sz + gen * sz
+             + (0.0 if write else gen * 4) + ev[sl].sum() * (sz + 4) + hits[sl].sum() * sz
+             + cnt[sl, 4].sum() * 4 + appended[sl].sum() * state)
+        out.append(b)
+    return np.array(out, dtype=np.float64)
 
 
 def particle_steps(cnt: np.ndarray) -> int:
@@ -360,8 +373,9 @@ def main():
     if not args.no_kernel_timing:
         rows, cnt2 = kernel_timing(sim)
         assert np.array_equal(cnt2, cnt), "step-by-step run differs from the graph run"
-        b = alg_bytes(cnt2, prob.state_fp64, general=rows[:, 3],
-                      z_every=sim.tuning()["z_every"])
+        tune = sim.tuning()
+        b = alg_bytes(cnt2, prob.state_fp64, launches=rows, z_every=tune["z_every"],
+                      sub_steps=tune["sub_steps"])
         ms, c_ms = rows[:, 0], rows[:, 1]
         achieved = b.sum() / (ms.sum() * 1e-3) / 1e9
         traffic = measured_traffic() if args.workload == "batched" else None
@@ -370,6 +384,7 @@ def main():
                     traffic=None if traffic is None else round(traffic, 0))
         left = float(rows[:, 3].sum() / max(1.0, rows[:, 2:4].sum()))
         extra["step_kernel"] = dict(kernel="k_step", launches=int(len(rows)),
+                                    steps_per_launch=int(tune["sub_steps"]),
                                     mean_launch_ms=round(float(ms.mean()), 4),
                                     alg_bytes_per_launch=float(b.mean()),
                                     bytes_per_particle_step=round(float(b.sum() / ps), 2),

@@ -137,6 +137,9 @@ typedef struct {
                              its z every z_every steps (1..8) and at the end of every
                              pic_step call; in between z is recomputed from the stored
                              value by repeating the straight flights exactly */
+  int32_t sub_steps;      /* steps advanced per kernel launch (1 or 2): a carrier that
+                             stays on the common path does them from registers, with one
+                             pass over its state; z_every is rounded up to a multiple */
 } pic_tuning;
 
 /* Where things live inside the workspace (byte offsets), for inspection and tests. */
@@ -166,7 +169,8 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
  * created at the start of step n (host array; each row must sum to n_primaries). */
 pic_status pic_inject(pic_ctx* ctx, const int64_t* sched);
 
-/* Enqueue n steps (the next ones after those already run), one kernel launch each. */
+/* Enqueue n steps (the next ones after those already run): one kernel launch per
+ * pic_tuning.sub_steps steps. */
 pic_status pic_step(pic_ctx* ctx, int32_t n);
 
 /* Enqueue one compaction pass now (slabs whose dead slots exceed
@@ -211,17 +215,17 @@ pic_status pic_layout_of(const pic_ctx* ctx, pic_layout* out);
 pic_status pic_autotune(pic_ctx* ctx, int32_t trial_steps, pic_tuning* best);
 
 /* Per-launch timing, for measurement.  pic_time_kernels(ctx, 1) makes the following
- * pic_step calls launch directly (no graph) and record HIP events around each step's
+ * pic_step calls launch directly (no graph) and record HIP events around each step-kernel
  * launch and its compaction; pic_time_kernels(ctx, 0) stops.  Either call synchronizes
  * and drops the events recorded so far. */
 pic_status pic_time_kernels(pic_ctx* ctx, int32_t enable);
 
-/* Synchronize and report the steps timed since timing was enabled: out[k*4 + 0..3] =
+/* Synchronize and report the launches timed since timing was enabled: out[k*6 + 0..5] =
  * milliseconds of the step launch, of the compaction after it (about 0 when none ran),
- * then the carriers whose step took the common path (no boundary, certainly no event)
- * and the ones that took the general path (host array, up to max_steps rows; *n_out =
- * steps recorded).  The recorded
- * events are dropped, except when out is NULL: then only *n_out is set. */
+ * the carrier-steps that took the common path (no boundary, certainly no event) and
+ * the ones that took the general path, the launch's first step and its number of steps
+ * (host array, up to max_steps rows; *n_out = launches recorded).  The recorded events
+ * are dropped, except when out is NULL: then only *n_out is set. */
 pic_status pic_kernel_times(pic_ctx* ctx, double* out, int32_t max_steps, int32_t* n_out);
 
 void pic_destroy(pic_ctx* ctx);

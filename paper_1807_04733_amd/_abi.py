@@ -64,7 +64,8 @@ class PicConfig(C.Structure):
 
 class PicTuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("grid", C.c_int32), ("compact_every", C.c_int32),
-                ("compact_frac", C.c_float), ("use_graph", C.c_int32), ("z_every", C.c_int32)]
+                ("compact_frac", C.c_float), ("use_graph", C.c_int32), ("z_every", C.c_int32),
+                ("sub_steps", C.c_int32)]
 
 
 class PicLayout(C.Structure):

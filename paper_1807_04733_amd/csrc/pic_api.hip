@@ -235,7 +235,7 @@ struct pic_ctx {
   // per-launch timing: events before and after each step launch and after its compaction
   bool timing = false;
   std::vector<std::array<hipEvent_t, 3>> tev;
-  std::vector<int> tstep;
+  std::vector<int> tstep, tnsub;
 
   template <typename T>
   T* at(int64_t off) const { return off < 0 ? nullptr : (T*)(ws + off); }
@@ -249,6 +249,7 @@ void drop_events(pic_ctx* c) {
       if (e) (void)hipEventDestroy(e);
   c->tev.clear();
   c->tstep.clear();
+  c->tnsub.clear();
 }
 
 void drop_graph(pic_ctx* c) {
@@ -259,13 +260,33 @@ void drop_graph(pic_ctx* c) {
   c->g_start = c->g_n = -1;
 }
 
-// Dynamic LDS of one step launch: [density | current] histograms, then per wave a
-// newborn queue and a general-path slot queue.
-size_t lds_for(const pic_ctx* c, int block, bool dens_step) {
-  const size_t dens = dens_step && c->dens_lds ? (size_t)c->lds_dens_words * 4 : 0;
-  const size_t cur_at = (dens + 15) & ~(size_t)15;
-  const size_t q_at = (cur_at + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
-  return q_at + (size_t)(block / 64) * (kChildQueueBytes + kSlowQueueBytes);
+// Dynamic LDS layout of one step launch over n_sub sub-steps: the density slices (of the
+// sub-steps that deposit density, when density goes to LDS), the current slices, then the
+// per-wave queues.  Fills the offsets in `a` (if given) and returns the bytes.
+size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, const int* cur_on,
+                   StepArgs* a) {
+  size_t off = 0;
+  for (int j = 0; j < kMaxSub; ++j) {
+    const bool d = j < n_sub && dens_on[j] && c->dens_lds;
+    if (a) a->lds_dens_at[j] = d ? (int32_t)off : -1;
+    if (d) off = (off + (size_t)c->lds_dens_words * 4 + 15) & ~(size_t)15;
+  }
+  for (int j = 0; j < kMaxSub; ++j) {
+    const bool u = j < n_sub && cur_on[j];
+    if (a) a->lds_cur_at[j] = u ? (int32_t)off : -1;
+    if (u) off = (off + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
+  }
+  if (a) {
+    a->lds_q_at = (int32_t)off;
+    a->lds_q_bytes = (int32_t)step_queue_bytes(n_sub);
+  }
+  return off + (size_t)(block / 64) * step_queue_bytes(n_sub);
+}
+
+// LDS of a one-step launch that deposits both moments (the largest one-step layout).
+size_t lds_for(const pic_ctx* c, int block) {
+  const int on[kMaxSub] = {1, 1};
+  return step_layout(c, block, 1, on, on, nullptr);
 }
 
 // Largest dynamic LDS a step launch may use: the device's per-workgroup limit minus the
@@ -362,32 +383,66 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
   const int n_slabs = (int)c->plan.slab_inst.size();
   int grid = c->tune.grid > 0 ? c->tune.grid : 512;
   grid = std::max(1, std::min(grid, n_slabs));
-  const int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
-  for (int s = start; s < start + n; ++s) {
+  const int T = std::max(1, std::min(c->tune.sub_steps, kMaxSub));
+  // write-back period: a multiple of the steps per launch
+  int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
+  K = std::min(kMaxZEvery / T * T, (K + T - 1) / T * T);
+  for (int s = start; s < start + n;) {
+    // launches of T steps, aligned to the call's start; the write-back periods are
+    // multiples of T, so only the last sub-step of a launch ever stores z
+    int ns = std::min(T, start + n - s);
     StepArgs a = step_args(c, s);
-    a.z_phase = (s - start) % K;
-    a.z_write = (a.z_phase == K - 1 || s == start + n - 1) ? 1 : 0;
+    int dens_on[kMaxSub] = {0, 0}, cur_on[kMaxSub] = {0, 0};
+    for (int j = 0; j < kMaxSub; ++j) {
+      const int sj = s + j;
+      dens_on[j] = j < ns && (sj % c->cfg.dens_stride) == 0;
+      cur_on[j] = j < ns && (sj % c->cfg.cur_stride) == 0;
+    }
+    // one step at a time where two density slices do not fit next to each other, or where
+    // the first step would have to store z
+    const bool first_writes = (s - start) % K == K - 1 || s == start + n - 1;
+    if (ns > 1 && (first_writes ||
+                   step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) > c->max_lds)) {
+      ns = 1;
+      dens_on[1] = cur_on[1] = 0;
+    }
+    a.n_sub = ns;
+    for (int j = 0; j < kMaxSub; ++j) {
+      const int sj = s + j;
+      a.sub_dens_on[j] = dens_on[j];
+      a.sub_cur_on[j] = cur_on[j];
+      a.sub_dens_slot[j] = sj / c->cfg.dens_stride;
+      a.sub_cur_slot[j] = sj / c->cfg.cur_stride;
+      a.sub_z_phase[j] = (sj - start) % K;
+      a.sub_z_write[j] = j < ns && (a.sub_z_phase[j] == K - 1 || sj == start + n - 1) ? 1 : 0;
+    }
+    a.z_phase = a.sub_z_phase[0];
+    a.z_write = a.sub_z_write[0];
     StepLaunch L;
     std::memset(&L, 0, sizeof(L));
     L.grid = grid;
     L.block = c->tune.block;
-    L.lds = lds_for(c, c->tune.block, a.dens_on != 0);
+    L.lds = step_layout(c, c->tune.block, ns, dens_on, cur_on, &a);
     hipEvent_t* ev = nullptr;
     if (c->timing) {
       c->tev.emplace_back();
       c->tstep.push_back(s);
+      c->tnsub.push_back(ns);
       ev = c->tev.back().data();
       for (int k = 0; k < 3; ++k) ev[k] = nullptr;
       for (int k = 0; k < 3; ++k) HIP_TRY(hipEventCreate(&ev[k]));
       for (int k = 0; k < 2; ++k) L.ev[k] = ev[k];
     }
     HIP_TRY(launch_step(a, fp64, L, c->stream));
-    if (c->tune.compact_every > 0 && !c->plan.debug && (s + 1) % c->tune.compact_every == 0 &&
-        s + 1 < c->cfg.n_steps) {
+    bool compact = false;
+    for (int j = 0; j < ns; ++j)
+      compact = compact || (c->tune.compact_every > 0 && (s + j + 1) % c->tune.compact_every == 0);
+    if (compact && !c->plan.debug && s + ns < c->cfg.n_steps) {
       CompactArgs ca = compact_args(c);
       HIP_TRY(launch_compact(ca, fp64, c->tune.block, c->stream));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], c->stream));
+    s += ns;
   }
   return PIC_OK;
 }
@@ -509,6 +564,7 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
   c->tune.compact_frac = 0.15f;
   c->tune.use_graph = 1;
   c->tune.z_every = 4;
+  c->tune.sub_steps = 1;
   // LDS per workgroup: the density slice and the current slice of the largest instance,
   // plus one newborn queue per wave.  The density histogram goes to LDS when it fits
   // next to the queues of a 256-thread block; otherwise density uses global atomics.
@@ -519,11 +575,12 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
   c->lds_dens_words = dens_words;
   c->dens_lds = true;
   c->max_lds = device_lds_limit();
-  if (lds_for(c, 256, true) > c->max_lds) {
+  if (lds_for(c, 256) > c->max_lds) {
     c->dens_lds = false;
     c->lds_dens_words = 0;
   }
-  if (lds_for(c, 64, false) > c->max_lds) {
+  const int none[kMaxSub] = {0, 0}, cur0[kMaxSub] = {1, 0};
+  if (step_layout(c, 64, 1, none, cur0, nullptr) > c->max_lds) {
     delete c;
     return fail(PIC_EINVAL, "too many depth bins for the LDS current histogram");
   }
@@ -635,7 +692,8 @@ pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
   if (t->z_every < 1 || t->z_every > kMaxZEvery) return fail(PIC_EINVAL, "z_every must be 1..8");
-  if (lds_for(c, b, true) > c->max_lds)
+  if (t->sub_steps < 1 || t->sub_steps > kMaxSub) return fail(PIC_EINVAL, "sub_steps must be 1 or 2");
+  if (lds_for(c, b) > c->max_lds)
     return fail(PIC_EINVAL, "block too large for the LDS histograms of this configuration");
   c->tune = *t;
   drop_graph(c);
@@ -822,7 +880,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   pic_tuning win = cur;
   // stage 1: workgroup size and persistent grid
   for (int block : {128, 256, 512}) {
-    if (lds_for(c, block, true) > c->max_lds) continue;
+    if (lds_for(c, block) > c->max_lds) continue;
     for (int grid : {256, 512, 1024, 2048}) {
       pic_tuning t = cur;
       t.block = block;
@@ -859,16 +917,23 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
       }
     }
   }
-  // stage 3: write-back period of z on the common path
-  for (int k : {1, 2, 4, 8}) {
-    pic_tuning t = win;
-    t.z_every = k;
-    float ms = 0;
-    pic_status st = time_trial(c, t, steps2, &ms);
-    if (st != PIC_OK) return st;
-    if (ms < best_ms) {
-      best_ms = ms;
-      win = t;
+  // stage 3: steps per launch and write-back period of z on the common path
+  {
+    const pic_tuning base = win;
+    for (int ns : {1, 2}) {
+      for (int k : {1, 2, 4, 8}) {
+        if (k % ns) continue;
+        pic_tuning t = base;
+        t.sub_steps = ns;
+        t.z_every = k;
+        float ms = 0;
+        pic_status st = time_trial(c, t, steps2, &ms);
+        if (st != PIC_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          win = t;
+        }
+      }
     }
   }
   win.use_graph = 1;
@@ -906,12 +971,18 @@ pic_status pic_kernel_times(pic_ctx* c, double* out, int32_t max_steps, int32_t*
     float f = 0, m = 0;
     HIP_TRY(hipEventElapsedTime(&f, ev[0], ev[1]));
     HIP_TRY(hipEventElapsedTime(&m, ev[1], ev[2]));
-    const int s = c->tstep[k];
-    double* o = out + (size_t)k * 4;
+    const int s = c->tstep[k], ns = c->tnsub[k];
+    double* o = out + (size_t)k * 6;
     o[0] = f;
     o[1] = m;
-    o[2] = (double)stats[(size_t)s * 2];
-    o[3] = (double)stats[(size_t)s * 2 + 1];
+    o[2] = 0.0;
+    o[3] = 0.0;
+    for (int j = 0; j < ns; ++j) {
+      o[2] += (double)stats[(size_t)(s + j) * 2];
+      o[3] += (double)stats[(size_t)(s + j) * 2 + 1];
+    }
+    o[4] = s;
+    o[5] = ns;
   }
   *n_out = (int32_t)c->tev.size();
   drop_events(c);

@@ -27,6 +27,9 @@ __device__ __forceinline__ uint32_t key_step(uint32_t k, uint32_t w) {
 
 __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
                                           uint32_t k0, uint32_t k1) {
+  // the key is the same for every lane: keep it (and its schedule) in scalar registers
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t m0 = (uint64_t)x0 * 0xD2511F53ull;

@@ -34,6 +34,8 @@ constexpr uint32_t kDead = 0x80000000u;
 constexpr int kStampShift = 5;
 constexpr uint32_t kStampMask = 0x7u;
 constexpr int kMaxZEvery = 8;
+// Steps one launch of the step kernel may advance.
+constexpr int kMaxSub = 2;
 
 // Device status bits.
 constexpr uint32_t kStOverflow = 1u;
@@ -99,6 +101,15 @@ struct StepArgs {
   // were straight flights and are recomputed.  z_write: this step stores z and clears
   // the stamps (the last step of a write-back period or of a pic_step call).
   int32_t z_phase, z_write;
+  // The steps step .. step + n_sub - 1 that one launch of the step kernel advances
+  // (sub-step j = step + j), and the byte offsets of their LDS histogram slices (-1: the
+  // sub-step deposits no such moment) and of the per-wave queues.
+  int32_t n_sub;
+  int32_t sub_dens_on[kMaxSub], sub_cur_on[kMaxSub];
+  int32_t sub_dens_slot[kMaxSub], sub_cur_slot[kMaxSub];
+  int32_t sub_z_phase[kMaxSub], sub_z_write[kMaxSub];
+  int32_t lds_dens_at[kMaxSub], lds_cur_at[kMaxSub];
+  int32_t lds_q_at, lds_q_bytes;
 };
 
 struct AdjArgs {
@@ -129,9 +140,15 @@ struct CompactArgs {
   double* r;                   // adjoint partial returns moved along, or null
 };
 
-// bytes of one wave's newborn queue and general-path slot queue in dynamic LDS
-constexpr size_t kChildQueueBytes = 128 * (8 + 4 * 4);
+// bytes of one wave's newborn queue (step kernel) and general-path slot queue (adjoint
+// replay) in dynamic LDS
+constexpr size_t kChildQueueBytes = 64 * (8 + 4 * 4);
 constexpr size_t kSlowQueueBytes = 128 * 4;
+// bytes of one wave's queues in the step kernel: newborns, then the slot queues of
+// sub-step 0 (128 entries) and, in two-step launches, of sub-step 1 (256 entries)
+constexpr size_t step_queue_bytes(int n_sub) {
+  return kChildQueueBytes + 128 * 4 + (n_sub > 1 ? 256 * 4 : 0);
+}
 
 // Launch shape of one step.
 struct StepLaunch {

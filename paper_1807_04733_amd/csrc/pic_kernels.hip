@@ -25,45 +25,53 @@ namespace pic {
 
 // Compile-time launch modes of the step kernel.
 constexpr int kModeDebug = 1;       // keep per-particle event counts
-constexpr int kModeDensLds = 2;     // this step deposits density into LDS
-constexpr int kModeDensGlobal = 4;  // this step deposits density with global atomics
-constexpr int kModeCur = 8;         // this step deposits the current
+constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slice does not fit)
 
-template <int MODE>
-__device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
-                                        unsigned long long* s_cur, const uint32_t* s_edges,
-                                        double z, double mu, uint32_t E, uint32_t fl, double v) {
+// Compile-time sub-step index for the generic lambdas of k_step.
+template <int V>
+struct Sub {
+  static constexpr int value = V;
+};
+
+// Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
+// sub-step (density per (z, E, spin), current per (z, spin)), or density to the global
+// bins when its slice does not fit in LDS.
+template <int MODE, int J>
+__device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
+                                        const uint32_t* s_edges, double z, double mu, uint32_t E,
+                                        uint32_t fl, double v) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
-  if (MODE & (kModeDensLds | kModeDensGlobal)) {
+  if (a.sub_dens_on[J]) {
     const int eb = a.n_ebins > 1 ? energy_bin(s_edges, a.n_ebins, E) : 0;
     const int idx = (zb * a.n_ebins + eb) * 2 + s;
-    if (MODE & kModeDensLds) {
-      atomicAdd(&s_dens[idx], 1u);
-    } else {
-      const int64_t g = I.dens_off + (int64_t)a.dens_slot * I.nz * a.n_ebins * 2 + idx;
+    if (MODE & kModeDensGlobal) {
+      const int64_t g = I.dens_off + (int64_t)a.sub_dens_slot[J] * I.nz * a.n_ebins * 2 + idx;
       atomicAdd((unsigned long long*)&a.dens[g], 1ull);
+    } else {
+      atomicAdd((uint32_t*)(dyn + a.lds_dens_at[J]) + idx, 1u);
     }
   }
-  if (MODE & kModeCur) {
+  if (a.sub_cur_on[J]) {
     const double vm = v * mu;
     // round-half-even to an integer by adding 1.5*2^52 (|vm*2^32| < 2^51): the low
     // mantissa bits then hold the integer, identical to rint()
     const double sh = vm * 4294967296.0 + 0x1.8p52;
     const long long val = __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
-    atomicAdd(&s_cur[zb * 2 + s], (unsigned long long)val);
+    atomicAdd((unsigned long long*)(dyn + a.lds_cur_at[J]) + zb * 2 + s, (unsigned long long)val);
   }
 }
 
-template <int MODE>
-__device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens,
-                           unsigned long long* s_cur) {
-  __syncthreads();
-  if (MODE & kModeDensLds) {
+// Merge sub-step J's LDS histogram slices of the workgroup's instance into the int64 bins
+// (non-zero entries only) and clear them.
+template <int MODE, int J>
+__device__ void flush_bins(const StepArgs& a, const DevInst& I, unsigned char* dyn) {
+  if (!(MODE & kModeDensGlobal) && a.sub_dens_on[J]) {
+    uint32_t* s_dens = (uint32_t*)(dyn + a.lds_dens_at[J]);
     const int n = I.nz * a.n_ebins * 2;
     unsigned long long* g =
-        (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.dens_slot * n);
+        (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.sub_dens_slot[J] * n);
     for (int b = threadIdx.x; b < n; b += blockDim.x) {
       const uint32_t v = s_dens[b];
       if (v) {
@@ -72,9 +80,11 @@ __device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens
       }
     }
   }
-  if (MODE & kModeCur) {
+  if (a.sub_cur_on[J]) {
+    unsigned long long* s_cur = (unsigned long long*)(dyn + a.lds_cur_at[J]);
     const int n = I.nz * 2;
-    unsigned long long* g = (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.cur_slot * n);
+    unsigned long long* g =
+        (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.sub_cur_slot[J] * n);
     for (int b = threadIdx.x; b < n; b += blockDim.x) {
       const unsigned long long v = s_cur[b];
       if (v) {
@@ -83,21 +93,20 @@ __device__ void flush_bins(const StepArgs& a, const DevInst& I, uint32_t* s_dens
       }
     }
   }
+}
+
+template <int MODE, int T>
+__device__ void flush_all(const StepArgs& a, const DevInst& I, unsigned char* dyn) {
+  __syncthreads();
+  flush_bins<MODE, 0>(a, I, dyn);
+  if constexpr (T > 1) flush_bins<MODE, 1>(a, I, dyn);
   __syncthreads();
 }
 
-__device__ __forceinline__ void wave_add(unsigned long long* c, bool pred) {
-  const uint64_t m = __ballot(pred);
-  if (m) {
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    if (__lane_id() == leader) atomicAdd(c, (unsigned long long)__popcll(m));
-  }
-}
-
-// Newborn secondaries wait in a wave-private LDS queue and are finished 64 at a time, so
-// the spawn draw, the newborn's half step, its deposit and its append run as full
-// waves instead of once per wave for a few lanes.
-constexpr int kQ = 128;
+// Newborn secondaries of one general pass wait in a wave-private LDS queue and are
+// finished right after it, 64 at a time, so the spawn draw, the newborn's half step, its
+// deposit and its append run as full waves instead of once per wave for a few lanes.
+constexpr int kQ = 64;
 struct ChildQueue {  // kChildQueueBytes
   double z[kQ];
   uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ];
@@ -118,105 +127,55 @@ struct LaneCounts {
   uint32_t dep, tr, ri, rs;
 };
 
-// Finish the top n entries of a wave's queue: spawn draw (direction, spin from the
-// layer's equilibrium polarisation, lineage), second half step, deposit and append.
-template <typename F, int MODE>
-__device__ __forceinline__ void drain_children(const StepArgs& a, const DevInst& I, ChildQueue& Q,
-                                               int qn, int n, uint32_t* s_dens,
-                                               unsigned long long* s_cur, const uint32_t* s_edges,
-                                               int* s_app, const SlabPtrs<F>& sp, int tail0,
-                                               int cap, LaneCounts& lc, bool& bad) {
-  constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  const int lane = __lane_id();
-  const bool act = lane < n;
-  const int idx = act ? qn - n + lane : 0;
-  double cz = Q.z[idx];
-  const uint32_t lo = Q.lo[idx], phi = Q.hi[idx], cE = Q.E[idx], pfl = Q.fl[idx];
-  if (act) {
-    const uint4 sw = philox10(lo, phi, (uint32_t)a.step, kTagSpawn, a.key0, a.key1);
-    const int l = layer_of(pfl);
-    double cmu = to_store<F>(dircos(sw.x));
-    const uint32_t cs = u01(sw.y) < I.lay[l].w ? 0u : 1u;
-    uint32_t lin = sw.z;
-    if (lin == 0u || lin == phi) {
-      lin = sw.w | 1u;
-      if (lin == phi) lin ^= 2u;
-    }
-    const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
-    uint32_t cfl = cs | (pfl & ~kSpinMask) | (z_next << kStampShift);
-    HitCounts h{0, 0, 0};
-    LayCache cc = load_lay(I, l, (int)cs);
-    half_push_c(I, cc, cz, cmu, cfl, cE, lo, lin, (uint32_t)a.step, kTagHalf2, a.h, a.key0,
-                a.key1, h, bad);
-    cz = to_store<F>(cz);
-    deposit<MODE>(a, I, s_dens, s_cur, s_edges, cz, cmu, cE, cfl, cc.v);
-    lc.dep += 1;
-    lc.tr += h.tr;
-    lc.ri += h.ri;
-    lc.rs += h.rs;
-    const uint64_t m = __ballot(1);
-    int off = 0;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    if (lane == leader) off = atomicAdd(s_app, __popcll(m));
-    off = __shfl(off, leader);
-    const uint32_t pos = (uint32_t)(tail0 + off + prefix_count(m));
-    if ((int)pos < cap) {
-      sp.z[pos] = (F)cz;
-      sp.mu[pos] = (F)cmu;
-      sp.E[pos] = cE;
-      sp.uid[pos] = (uint64_t)lo | ((uint64_t)lin << 32);
-      sp.fl[pos] = cfl;
-      if (DEBUG) sp.ev[pos] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
-    } else {
-      atomicOr(a.status, kStOverflow);
-    }
-  }
-}
+// Per-wave queues of general-path slots: sub-step 0 holds < 64 + 64 entries; sub-step 1
+// also receives the survivors and newborns of a sub-step-0 general pass (< 64 + 64 + 128).
+constexpr int kSlowQ0 = 128;
+constexpr int kSlowQ1 = 256;
 
-// Slots whose step needs the general path (a boundary hit, or a draw below x that may be
-// an event) wait in a wave-private LDS queue; their state is still untouched in HBM and
-// is re-read when 64 have gathered, so the general path runs as full waves while the
-// common step (no hit, certainly no event) runs without divergent branches.
-constexpr int kSlowQ = 128;
-
-template <typename F, int MODE>
+// One launch of k_step advances every carrier of every instance by T (1 or 2) steps of the
+// Strang splitting.  A workgroup takes one slab at a time; each lane takes one carrier
+// per iteration and runs its T steps from registers while they stay on the common path:
+// no layer boundary in either half step and a scattering draw at or above x = dt/tau_eff
+// (which is above p = 1 - exp(-x), so no event can happen).  The first step that leaves
+// the common path puts the carrier's slot into the wave's LDS queue of that sub-step; the
+// state in HBM is still the one stored before it (its z stamp says which straight
+// flights to redo).  A queue of 64 slots runs the general path as a full wave; the
+// survivors and newborns of a sub-step-0 general pass continue with sub-step 1 the same
+// way.  New primaries (source term, Eq. 17) of a sub-step are appended with their initial
+// state and queued for its general path.
+template <typename F, int T, int MODE>
 __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  // dynamic LDS: [density histogram | current histogram | child queue per wave |
-  //               general-path slot queue per wave]
+  // dynamic LDS: [histogram slices of the sub-steps | per wave: newborn queue, slot
+  // queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
   extern __shared__ __align__(16) unsigned char dyn[];
-  uint32_t* s_dens = (uint32_t*)dyn;
-  const size_t cur_at = ((size_t)a.lds_dens_words * 4 + 15) & ~(size_t)15;
-  unsigned long long* s_cur = (unsigned long long*)(dyn + cur_at);
-  const size_t q_at = (cur_at + (size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15;
-  ChildQueue* s_q = (ChildQueue*)(dyn + q_at);
-  uint32_t* s_slow = (uint32_t*)(dyn + q_at + (size_t)(blockDim.x >> 6) * kChildQueueBytes);
   __shared__ DevInst s_inst;
-  __shared__ unsigned long long s_cnt[kNC];
+  __shared__ unsigned long long s_cnt[T][kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
   __shared__ int s_slab, s_app, s_dead;
-  __shared__ unsigned long long s_fast, s_left;
+  __shared__ unsigned long long s_fast[T], s_left[T];
 
   const int tid = threadIdx.x;
   const int lane = __lane_id();
   const int wave = tid >> 6;
-  if (tid == 0) {
-    s_fast = 0;
-    s_left = 0;
-  }
-  uint32_t n_fast = 0, n_left = 0;
-  for (int i = tid; i < a.lds_dens_words; i += blockDim.x) s_dens[i] = 0;
-  for (int i = tid; i < a.lds_cur_words; i += blockDim.x) s_cur[i] = 0;
+  for (int i = tid; i < a.lds_q_at / 4; i += blockDim.x) ((uint32_t*)dyn)[i] = 0;
   for (int i = tid; i < a.n_ebins; i += blockDim.x) s_edges[i] = a.e_edges[i];
-  if (tid < kNC) s_cnt[tid] = 0;
+  for (int i = tid; i < T * kNC; i += blockDim.x) (&s_cnt[0][0])[i] = 0;
+  if (tid < T) {
+    s_fast[tid] = 0;
+    s_left[tid] = 0;
+  }
+  uint32_t n_fast[T], n_left[T];
+#pragma unroll
+  for (int j = 0; j < T; ++j) n_fast[j] = n_left[j] = 0;
 
   F* gz = (F*)a.z;
   F* gmu = (F*)a.mu;
-  const uint32_t step = (uint32_t)a.step;
-  // stamp of every z this step stores (0 when the step ends a write-back period)
-  const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
-  ChildQueue& Q = s_q[wave];
-  uint32_t* SQ = s_slow + wave * kSlowQ;
+  const uint32_t step0 = (uint32_t)a.step;
+  unsigned char* wq = dyn + a.lds_q_at + (size_t)wave * a.lds_q_bytes;
+  ChildQueue& Q = *(ChildQueue*)wq;
+  uint32_t* const SQ0 = (uint32_t*)(wq + kChildQueueBytes);
+  uint32_t* const SQ1 = SQ0 + kSlowQ0;
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   int cur_inst = -1;
   bool bad = false;
@@ -224,11 +183,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   for (;;) {
     if (tid == 0) s_slab = atomicAdd(&a.queue[a.step], 1);
     __syncthreads();
-    const int slab = s_slab;
+    const int slab = __builtin_amdgcn_readfirstlane(s_slab);
     if (slab >= a.n_slabs) break;
     const int inst = a.slab_inst[slab];
     if (inst != cur_inst) {
-      if (cur_inst >= 0) flush_bins<MODE>(a, s_inst, s_dens, s_cur);
+      if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
       const uint4* src = (const uint4*)&a.inst[inst];
       uint4* dst = (uint4*)&s_inst;
       for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
@@ -246,23 +205,94 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     const int64_t kk = a.slab_k[slab];
     const int64_t S = I.n_slabs;
     const int64_t* cum = a.inj_cum + (int64_t)inst * (a.n_steps + 1);
-    const int64_t f0 = count_mod(cum[step], kk, S);
-    const int n_inj = (int)(count_mod(cum[step + 1], kk, S) - f0);
-    const int total = tail0 + n_inj;
-    if (tid == 0 && n_inj) atomicAdd(&s_cnt[PIC_C_INJECTED], (unsigned long long)n_inj);
+    // primaries of sub-step j are the instance's primaries [cum[step0+j], cum[step0+j+1])
+    // that fall in this slab (index = slab k mod S)
+    const int64_t f00 = count_mod(cum[step0], kk, S);
+    const int64_t f01 = count_mod(cum[step0 + 1], kk, S);
+    const int n_inj0 = (int)(f01 - f00);
+    int n_inj1 = 0;
+    if constexpr (T > 1) n_inj1 = (int)(count_mod(cum[step0 + 2], kk, S) - f01);
+    const int total = tail0 + n_inj0 + n_inj1;
+    if (tid == 0) {
+      if (n_inj0) atomicAdd(&s_cnt[0][PIC_C_INJECTED], (unsigned long long)n_inj0);
+      if constexpr (T > 1)
+        if (n_inj1) atomicAdd(&s_cnt[T - 1][PIC_C_INJECTED], (unsigned long long)n_inj1);
+    }
     const SlabPtrs<F> sp{gz + base, gmu + base, a.E + base, a.uid + base, a.flags + base,
                          DEBUG ? a.ev + base : nullptr};
-    LaneCounts lc{0, 0, 0, 0};
-    int qn = 0;  // wave-uniform fill of this wave's child queue
-    int sn = 0;  // wave-uniform fill of this wave's general-path queue
+    LaneCounts lc[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) lc[j] = LaneCounts{0, 0, 0, 0};
+    int qn = 0;   // wave-uniform fill of the newborn queue
+    int sn0 = 0;  // ... of the slot queue of sub-step 0
+    int sn1 = 0;  // ... of sub-step 1
+
+    auto wave_sync = [&]() __attribute__((always_inline)) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+
+    // ---- put the slots of the lanes with `pred` into the queue of sub-step J
+    auto push = [&](auto sub, bool pred, uint32_t slot) __attribute__((always_inline)) {
+      constexpr int J = decltype(sub)::value;
+      const uint64_t m = __ballot(pred);
+      if (m) {
+        if (J == 0) {
+          if (pred) SQ0[sn0 + prefix_count(m)] = slot;
+          sn0 += __popcll(m);
+        } else {
+          if (pred) SQ1[sn1 + prefix_count(m)] = slot;
+          sn1 += __popcll(m);
+        }
+        if (pred) n_left[J] += 1;
+      }
+    };
+
+    // ---- the common step of sub-step J from a position at its start (no replay
+    // needed), or the slot goes to the sub-step's queue.  `slot` holds the carrier whose
+    // stored z is that position (stamp = this sub-step's phase).
+    auto cont = [&](auto sub, bool act, uint32_t slot, double z, double mu, uint32_t E,
+                    uint32_t fl, uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
+      constexpr int J = decltype(sub)::value;
+      bool left = false;
+      if (act) {
+        const int l = layer_of(fl);
+        const LayCache c = load_lay(I, l, (int)(fl & kSpinMask));
+        const double zm = z + (c.v * mu) * a.h;
+        const uint4 w = philox10(lo, hi, step0 + J, kTagScat, a.key0, a.key1);
+        const double E_ev = (double)E * 0x1p-30;
+        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
+        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+        const double ze = zm + (c.v * mu) * a.h;
+        left = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        if (!left) {
+          const double zs = to_store<F>(ze);
+          deposit<MODE, J>(a, I, dyn, s_edges, zs, mu, E, fl, c.v);
+          lc[J].dep += 1;
+          n_fast[J] += 1;
+          if (a.sub_z_write[J]) {
+            sp.z[slot] = (F)zs;
+            if ((fl >> kStampShift) & kStampMask) sp.fl[slot] = fl & ~(kStampMask << kStampShift);
+          }
+        }
+      }
+      push(sub, left, slot);
+    };
 
     // ---------------------------------------------------------------- general path
-    // The whole step for one carrier: boundary hits, the exact scattering decision,
-    // elastic / inelastic events, absorption, the newborn's queueing, the append of a
-    // new primary and the write-back.  All lanes of the wave call it together; lanes
-    // with nothing to do pass a dead carrier.
-    auto general = [&](bool from_soa, bool is_new, uint32_t gi, double z, double mu,
-                       uint32_t E, uint32_t fl, uint32_t lo, uint32_t hi, uint64_t evp) {
+    // The whole of sub-step J for one carrier: boundary hits, the exact scattering
+    // decision, elastic / inelastic events, absorption, the newborn's queueing, the append
+    // of a new primary and the write-back.  All lanes of the wave call it together; lanes
+    // with nothing to do pass a dead carrier.  Returns whether the carrier is alive after
+    // the step, with its state and its slot.
+    auto general = [&](auto sub, bool from_soa, bool is_new, uint32_t gi, double& z, double& mu,
+                       uint32_t& E, uint32_t& fl, uint32_t lo, uint32_t hi, uint64_t evp,
+                       uint32_t& slot) __attribute__((always_inline)) -> bool {
+      constexpr int J = decltype(sub)::value;
+      const uint32_t step = step0 + J;
+      // stamp of the z this sub-step stores (0 when it ends a write-back period)
+      const uint32_t z_next = a.sub_z_write[J] ? 0u : (uint32_t)a.sub_z_phase[J] + 1u;
       const bool alive0 = !(fl & kDead);
       bool died = false, spawn = false;
       uint32_t dirty = 0;  // 1: mu, 2: E, 4: flags
@@ -298,9 +328,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           mu = to_store<F>(dircos(w.z));
           dirty |= 1u;
           if (elastic) {
-            atomicAdd(&s_cnt[PIC_C_EV_EL], 1ull);
+            atomicAdd(&s_cnt[J][PIC_C_EV_EL], 1ull);
           } else {
-            atomicAdd(&s_cnt[PIC_C_EV_EE], 1ull);
+            atomicAdd(&s_cnt[J][PIC_C_EV_EE], 1ull);
             const uint32_t E1 = __umulhi(w.w, E);
             E2 = E - E1;
             E = E1;
@@ -311,24 +341,24 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                 zmid = z;
                 flmid = fl;
                 if (DEBUG) evp += 1ull << 48;
-                atomicAdd(&s_cnt[PIC_C_SPAWNED], 1ull);
+                atomicAdd(&s_cnt[J][PIC_C_SPAWNED], 1ull);
               } else {
-                atomicAdd(&s_cnt[PIC_C_SEC_ABSORBED], 1ull);
-                atomicAdd(&s_cnt[PIC_C_E_ABSORBED], (unsigned long long)E2);
+                atomicAdd(&s_cnt[J][PIC_C_SEC_ABSORBED], 1ull);
+                atomicAdd(&s_cnt[J][PIC_C_E_ABSORBED], (unsigned long long)E2);
               }
             }
             if (E1 < a.e_min) {
               died = true;
-              atomicAdd(&s_cnt[PIC_C_ABSORBED], 1ull);
-              atomicAdd(&s_cnt[PIC_C_E_ABSORBED], (unsigned long long)E1);
+              atomicAdd(&s_cnt[J][PIC_C_ABSORBED], 1ull);
+              atomicAdd(&s_cnt[J][PIC_C_E_ABSORBED], (unsigned long long)E1);
             }
           }
         }
         if (!died) {
           half_push_c(I, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
           z = to_store<F>(z);
-          deposit<MODE>(a, I, s_dens, s_cur, s_edges, z, mu, E, fl, c.v);
-          lc.dep += 1;
+          deposit<MODE, J>(a, I, dyn, s_edges, z, mu, E, fl, c.v);
+          lc[J].dep += 1;
         } else {
           z = to_store<F>(z);
           fl |= kDead;
@@ -339,9 +369,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         if (fl != fl_in) dirty |= 4u;
         if (DEBUG) evp += ((uint64_t)hc.tr << 16) + ((uint64_t)(hc.ri + hc.rs) << 32);
       }
-      lc.tr += hc.tr;
-      lc.ri += hc.ri;
-      lc.rs += hc.rs;
+      lc[J].tr += hc.tr;
+      lc[J].ri += hc.ri;
+      lc[J].rs += hc.rs;
 
       // ---- queue the newborns: (mid-step position, parent uid, energy, layer | gen)
       const uint64_t mq = __ballot(spawn);
@@ -358,6 +388,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         }
         qn += __popcll(mq);
       }
+      slot = gi;
+      bool placed = from_soa;
       // ---- append the new primary (always, so that an absorbed one leaves its record)
       const uint64_t ma = __ballot(is_new);
       if (ma) {
@@ -367,7 +399,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         off = __shfl(off, leader);
         if (is_new) {
           const uint32_t pos = (uint32_t)(tail0 + off + prefix_count(ma));
+          slot = pos;
           if ((int)pos < cap) {
+            placed = true;
             sp.z[pos] = (F)z;
             sp.mu[pos] = (F)mu;
             sp.E[pos] = E;
@@ -388,22 +422,80 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
+      return alive0 && !died && placed;
     };
 
-    auto wave_sync = [&]() {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- finish the newborns of the last general pass of sub-step J (at most 64): spawn
+    // draw (direction, spin from the layer's equilibrium polarisation, lineage), second
+    // half step, deposit, append; with a further sub-step they continue with it
+    auto drain_kids = [&](auto sub) __attribute__((always_inline)) {
+      constexpr int J = decltype(sub)::value;
+      wave_sync();
+      const int n = qn;
+      qn = 0;
+      if (n == 0) return;
+      const uint32_t step = step0 + J;
+      const uint32_t z_next = a.sub_z_write[J] ? 0u : (uint32_t)a.sub_z_phase[J] + 1u;
+      const bool act = lane < n;
+      const int idx = act ? lane : 0;
+      double cz = Q.z[idx];
+      const uint32_t lo = Q.lo[idx], phi = Q.hi[idx], cE = Q.E[idx], pfl = Q.fl[idx];
+      wave_sync();
+      double cmu = 0.0;
+      uint32_t cfl = kDead, lin = 0, pos = 0;
+      bool placed = false;
+      if (act) {
+        const uint4 sw = philox10(lo, phi, step, kTagSpawn, a.key0, a.key1);
+        const int l = layer_of(pfl);
+        cmu = to_store<F>(dircos(sw.x));
+        const uint32_t cs = u01(sw.y) < I.lay[l].w ? 0u : 1u;
+        lin = sw.z;
+        if (lin == 0u || lin == phi) {
+          lin = sw.w | 1u;
+          if (lin == phi) lin ^= 2u;
+        }
+        cfl = cs | (pfl & ~kSpinMask) | (z_next << kStampShift);
+        HitCounts h{0, 0, 0};
+        LayCache cc = load_lay(I, l, (int)cs);
+        half_push_c(I, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0, a.key1, h,
+                    bad);
+        cz = to_store<F>(cz);
+        deposit<MODE, J>(a, I, dyn, s_edges, cz, cmu, cE, cfl, cc.v);
+        lc[J].dep += 1;
+        lc[J].tr += h.tr;
+        lc[J].ri += h.ri;
+        lc[J].rs += h.rs;
+        const uint64_t m = __ballot(1);
+        int off = 0;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        if (lane == leader) off = atomicAdd(&s_app, __popcll(m));
+        off = __shfl(off, leader);
+        pos = (uint32_t)(tail0 + off + prefix_count(m));
+        if ((int)pos < cap) {
+          placed = true;
+          sp.z[pos] = (F)cz;
+          sp.mu[pos] = (F)cmu;
+          sp.E[pos] = cE;
+          sp.uid[pos] = (uint64_t)lo | ((uint64_t)lin << 32);
+          sp.fl[pos] = cfl;
+          if (DEBUG) sp.ev[pos] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
+        } else {
+          atomicOr(a.status, kStOverflow);
+        }
+      }
+      if constexpr (J + 1 < T) cont(Sub<J + 1>{}, placed, pos, cz, cmu, cE, cfl, lo, lin);
     };
-    // finish the top n queued general-path slots (state re-read from HBM)
-    auto drain_slow = [&](int n) {
+
+    // re-read the top n slots of a sub-step's queue and bring z to the start of that step
+    auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, uint32_t& g, double& z,
+                         double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo, uint32_t& hi,
+                         uint64_t& evp) __attribute__((always_inline)) -> bool {
       wave_sync();
       const bool act = lane < n;
-      const uint32_t g = act ? SQ[sn - n + lane] : 0u;
+      g = act ? SQ[sn - n + lane] : 0u;
       sn -= n;
-      uint32_t fl = kDead, E = 0, lo = 0, hi = 0;
-      double z = 0.0, mu = 0.0;
-      uint64_t evp = 0;
+      wave_sync();
+      fl = kDead;
       if (act) {
         fl = sp.fl[g];
         z = (double)sp.z[g];
@@ -413,30 +505,93 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
         if (DEBUG) evp = sp.ev[g];
-        const int d = a.z_phase - (int)((fl >> kStampShift) & kStampMask);
+        const int d = phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
           const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
           z = replay_flights<F>(z, (c.v * mu) * a.h, d);
         }
       }
-      general(act, false, g, z, mu, E, fl, lo, hi, evp);
-      wave_sync();
+      return act;
     };
-    auto drain_kids = [&](int n) {
-      wave_sync();
-      drain_children<F, MODE>(a, I, Q, qn, n, s_dens, s_cur, s_edges, &s_app, sp, tail0, cap,
-                              lc, bad);
-      qn -= n;
-      wave_sync();
+    // ---- the last sub-step of the launch through the general path, for the top n slots
+    // of its queue
+    auto drain_last = [&](int n) __attribute__((always_inline)) {
+      uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0;
+      double z = 0.0, mu = 0.0;
+      uint64_t evp = 0;
+      const bool act = pop_state(T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
+                                 a.sub_z_phase[T - 1], g, z, mu, E, fl, lo, hi, evp);
+      general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, slot);
+      drain_kids(Sub<T - 1>{});
+    };
+    // ---- sub-step 0 of a two-step launch through the general path for the top n slots
+    // of its queue; survivors and newborns continue with sub-step 1
+    auto drain_first = [&](int n) __attribute__((always_inline)) {
+      if constexpr (T > 1) {
+        uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0;
+        double z = 0.0, mu = 0.0;
+        uint64_t evp = 0;
+        const bool act =
+            pop_state(SQ0, sn0, n, a.sub_z_phase[0], g, z, mu, E, fl, lo, hi, evp);
+        const bool surv = general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, slot);
+        cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi);
+        drain_kids(Sub<0>{});
+      }
+    };
+    // ---- a new primary of sub-step J (source term, Eq. 17), the k-th of the slab's
+    // share: its initial state is appended (so that even an absorbed one leaves its record)
+    // with the stamp of the start of its step, and its slot queued for the general path
+    auto inject = [&](auto sub, bool want, int64_t f0, int k) __attribute__((always_inline)) {
+      constexpr int J = decltype(sub)::value;
+      const uint64_t m = __ballot(want);
+      if (!m) return;
+      int off = 0;
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      if (lane == leader) off = atomicAdd(&s_app, __popcll(m));
+      off = __shfl(off, leader);
+      bool placed = false;
+      uint32_t pos = 0;
+      if (want) {
+        pos = (uint32_t)(tail0 + off + prefix_count(m));
+        const int64_t j = kk + S * (f0 + k);
+        const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
+        const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
+        double z0;
+        if (I.src_lambda > 0.0)
+          z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
+        else
+          z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
+        const double z = to_store<F>(z0);
+        const double mu = to_store<F>(dircos(w.y));
+        const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
+        const uint32_t E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
+        int l = 0;
+        for (int q = 1; q < I.n_layers; ++q)
+          if (I.lay[q].x <= z) l = q;
+        const uint32_t fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift) |
+                            ((uint32_t)a.sub_z_phase[J] << kStampShift);
+        if ((int)pos < cap) {
+          placed = true;
+          sp.z[pos] = (F)z;
+          sp.mu[pos] = (F)mu;
+          sp.E[pos] = E;
+          sp.uid[pos] = (uint64_t)root;
+          sp.fl[pos] = fl;
+          if (DEBUG) sp.ev[pos] = 0;
+        } else {
+          atomicOr(a.status, kStOverflow);
+        }
+      }
+      push(sub, placed, pos);
     };
 
     // The slot a lane will handle in its next iteration is fetched one iteration ahead,
     // unconditionally (a dead slot's fields are loaded too), so that no load waits on
-    // another and each wave keeps two particles' worth of loads in flight.
+    // another and each wave keeps two carriers' worth of loads in flight.
     F nz = 0, nmu = 0;
     uint32_t nE = 0, nfl = kDead;
     uint64_t nu = 0;
-    auto fetch = [&](int t) {
+    auto fetch = [&](int t) __attribute__((always_inline)) {
       if (t < tail0) {
         const uint32_t g = (uint32_t)t;
         nfl = sp.fl[g];
@@ -449,94 +604,83 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       }
     };
     fetch(wave * 64 + lane);
-    for (int tb = wave * 64; tb < total; tb += blockDim.x) {
-      const int t = tb + lane;
-      const F rz = nz, rmu = nmu;
-      const uint32_t rE = nE, rfl = nfl;
-      const uint64_t ru = nu;
-      fetch(t + (int)blockDim.x);
-      const bool have = t < total;
-      const bool from_soa = have && t < tail0;
-      const bool is_new = have && !from_soa;
-      const uint32_t gi = (uint32_t)t;
+    // Each iteration streams 64 slots (each lane adds at most one entry to one queue),
+    // then runs the general path on full queues; past the end it empties the queues.  The
+    // sub-step-1 queue then holds < 64 + 64 + 128 entries.
+    for (int tb = wave * 64;; tb += blockDim.x) {
+      const bool streaming = tb < total;
+      if (!streaming && sn0 == 0 && sn1 == 0) break;
+      if (streaming) {
+        const int t = tb + lane;
+        const F rz = nz, rmu = nmu;
+        const uint32_t rE = nE, rfl = nfl;
+        const uint64_t ru = nu;
+        fetch(t + (int)blockDim.x);
+        const bool have = t < total;
+        const bool from_soa = have && t < tail0;
+        const bool is_new0 = have && !from_soa && t < tail0 + n_inj0;
+        const bool is_new1 = have && t >= tail0 + n_inj0;
+        const uint32_t gi = (uint32_t)t;
 
-      // ---- common step: no boundary in either half step and a draw at or above
-      // x >= p, so certainly no event; identical arithmetic to the general path
-      bool slow = false;
-      if (from_soa && !(rfl & kDead)) {
-        const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
-        const LayCache c = load_lay(I, l, s);
-        const double mu = (double)rmu;
-        const uint32_t st = (rfl >> kStampShift) & kStampMask;
-        const double z0 = replay_flights<F>((double)rz, (c.v * mu) * a.h, a.z_phase - (int)st);
-        const double zm = z0 + (c.v * mu) * a.h;
-        const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
-                                 a.key1);
-        const double E_ev = (double)rE * 0x1p-30;
-        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
-        const double ze = zm + (c.v * mu) * a.h;
-        slow = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
-        if (!slow) {
-          const double zs = to_store<F>(ze);
-          deposit<MODE>(a, I, s_dens, s_cur, s_edges, zs, mu, rE, rfl, c.v);
-          if (a.z_write) {
-            sp.z[gi] = (F)zs;
+        // ---- the common steps of this launch, from registers
+        int left_at = -1;
+        if (from_soa && !(rfl & kDead)) {
+          const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
+          const LayCache c = load_lay(I, l, s);
+          const double mu = (double)rmu;
+          const double vmh = (c.v * mu) * a.h;
+          const uint32_t st = (rfl >> kStampShift) & kStampMask;
+          double z = replay_flights<F>((double)rz, vmh, a.sub_z_phase[0] - (int)st);
+          const double E_ev = (double)rE * 0x1p-30;
+          const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
+          const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+#pragma unroll
+          for (int j = 0; j < T; ++j) {
+            if (left_at < 0) {
+              const double zm = z + vmh;
+              const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step0 + j,
+                                       kTagScat, a.key0, a.key1);
+              const double ze = zm + vmh;
+              if (zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo) {
+                left_at = j;
+              } else {
+                z = to_store<F>(ze);
+                if (j == 0) deposit<MODE, 0>(a, I, dyn, s_edges, z, mu, rE, rfl, c.v);
+                if constexpr (T > 1)
+                  if (j == 1) deposit<MODE, T - 1>(a, I, dyn, s_edges, z, mu, rE, rfl, c.v);
+                lc[j].dep += 1;
+                n_fast[j] += 1;
+              }
+            }
+          }
+          if (left_at < 0 && a.sub_z_write[T - 1]) {
+            sp.z[gi] = (F)z;
             if (st) sp.fl[gi] = rfl & ~(kStampMask << kStampShift);
           }
-          lc.dep += 1;
-          n_fast += 1;
-        } else {
-          n_left += 1;
         }
+        push(Sub<0>{}, left_at == 0, gi);
+        if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi);
+        // ---- new primaries of each sub-step
+        inject(Sub<0>{}, is_new0, f00, t - tail0);
+        if constexpr (T > 1) inject(Sub<1>{}, is_new1, f01, t - tail0 - n_inj0);
       }
-      // ---- new primaries (source term, Eq. 17) take the general path at once
-      if (__ballot(is_new)) {
-        double z = 0.0, mu = 0.0;
-        uint32_t E = 0, fl = kDead, lo = 0;
-        if (is_new) {
-          const int64_t j = kk + S * (f0 + (t - tail0));
-          const uint32_t root = (uint32_t)(I.root_offset + (uint64_t)j);
-          const uint4 w = philox10(root, 0u, 0xFFFFFFFFu, kTagInject, a.key0, a.key1);
-          double z0;
-          if (I.src_lambda > 0.0)
-            z0 = I.src_lo - I.src_lambda * log1p(-u01(w.x) * I.src_cd);
-          else
-            z0 = I.src_lo + u01(w.x) * (I.src_hi - I.src_lo);
-          z = to_store<F>(z0);
-          mu = to_store<F>(dircos(w.y));
-          const uint32_t s = u01(w.z) < I.src_up ? 0u : 1u;
-          E = I.e_lo[s] + __umulhi(w.w, I.e_span[s]);
-          int l = 0;
-          for (int q = 1; q < I.n_layers; ++q)
-            if (I.lay[q].x <= z) l = q;
-          fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift);
-          lo = root;
-        }
-        general(false, is_new, gi, z, mu, E, fl, lo, 0u, 0ull);
-        if (qn >= 64) drain_kids(64);
+      const int need = streaming ? 64 : 1;
+      if (sn0 >= need) {
+        if constexpr (T > 1)
+          drain_first(sn0 < 64 ? sn0 : 64);
+        else
+          drain_last(sn0 < 64 ? sn0 : 64);
       }
-      // ---- queue the general-path slots; each general pass adds at most 64 newborns,
-      // so the newborn queue (128) is drained below 64 before every pass
-      const uint64_t ms = __ballot(slow);
-      if (ms) {
-        if (slow) SQ[sn + prefix_count(ms)] = gi;
-        sn += __popcll(ms);
-      }
-      if (sn >= 64) {
-        drain_slow(64);
-        if (qn >= 64) drain_kids(64);
-      }
+      if constexpr (T > 1)
+        while (sn1 >= need) drain_last(sn1 < 64 ? sn1 : 64);
     }
-    while (sn > 0) {
-      drain_slow(sn < 64 ? sn : 64);
-      if (qn >= 64) drain_kids(64);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if (lc[j].dep) atomicAdd(&s_cnt[j][PIC_C_ALIVE], (unsigned long long)lc[j].dep);
+      if (lc[j].tr) atomicAdd(&s_cnt[j][PIC_C_TRANSMIT], (unsigned long long)lc[j].tr);
+      if (lc[j].ri) atomicAdd(&s_cnt[j][PIC_C_REFL_IF], (unsigned long long)lc[j].ri);
+      if (lc[j].rs) atomicAdd(&s_cnt[j][PIC_C_REFL_SURF], (unsigned long long)lc[j].rs);
     }
-    while (qn > 0) drain_kids(qn < 64 ? qn : 64);
-    if (lc.dep) atomicAdd(&s_cnt[PIC_C_ALIVE], (unsigned long long)lc.dep);
-    if (lc.tr) atomicAdd(&s_cnt[PIC_C_TRANSMIT], (unsigned long long)lc.tr);
-    if (lc.ri) atomicAdd(&s_cnt[PIC_C_REFL_IF], (unsigned long long)lc.ri);
-    if (lc.rs) atomicAdd(&s_cnt[PIC_C_REFL_SURF], (unsigned long long)lc.rs);
     __syncthreads();
     if (tid == 0) {
       int nt = tail0 + s_app;
@@ -545,16 +689,21 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       a.slab_dead[slab] += s_dead;
     }
   }
-  if (cur_inst >= 0) flush_bins<MODE>(a, s_inst, s_dens, s_cur);
+  if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
   if (bad) atomicOr(a.status, kStHits);
-  if (n_fast) atomicAdd(&s_fast, (unsigned long long)n_fast);
-  if (n_left) atomicAdd(&s_left, (unsigned long long)n_left);
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    if (n_fast[j]) atomicAdd(&s_fast[j], (unsigned long long)n_fast[j]);
+    if (n_left[j]) atomicAdd(&s_left[j], (unsigned long long)n_left[j]);
+  }
   __syncthreads();
-  if (tid < kNC && s_cnt[tid])
-    atomicAdd((unsigned long long*)&a.counters[(int64_t)a.step * kNC + tid], s_cnt[tid]);
-  if (tid == 0) {
-    if (s_fast) atomicAdd(&a.stats[(int64_t)a.step * 2 + 0], s_fast);
-    if (s_left) atomicAdd(&a.stats[(int64_t)a.step * 2 + 1], s_left);
+  for (int i = tid; i < T * kNC; i += blockDim.x) {
+    const unsigned long long v = (&s_cnt[0][0])[i];
+    if (v) atomicAdd((unsigned long long*)&a.counters[(int64_t)a.step * kNC + i], v);
+  }
+  if (tid < T) {
+    if (s_fast[tid]) atomicAdd(&a.stats[((int64_t)a.step + tid) * 2 + 0], s_fast[tid]);
+    if (s_left[tid]) atomicAdd(&a.stats[((int64_t)a.step + tid) * 2 + 1], s_left[tid]);
   }
 }
 
@@ -647,58 +796,60 @@ __global__ void k_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, 
   }
 }
 
-template <typename F, int MODE>
+template <typename F, int T, int MODE>
 static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
-  if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
-  hipLaunchKernelGGL((k_step<F, MODE>), dim3(L.grid), dim3(L.block), L.lds, s, a);
-  if (L.ev[1]) (void)hipEventRecord(L.ev[1], s);
+  hipLaunchKernelGGL((k_step<F, T, MODE>), dim3(L.grid), dim3(L.block), L.lds, s, a);
 }
 
-template <typename F>
+template <typename F, int T>
 static hipError_t launch_prec(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s) {
   switch (mode) {
-#define PIC_MODE(m) \
-  case m:           \
-    launch_mode<F, m>(a, L, s); \
-    break;
-    PIC_MODE(0) PIC_MODE(1) PIC_MODE(2) PIC_MODE(3) PIC_MODE(4) PIC_MODE(5)
-    PIC_MODE(8) PIC_MODE(9) PIC_MODE(10) PIC_MODE(11) PIC_MODE(12) PIC_MODE(13)
-#undef PIC_MODE
-    default:
-      return hipErrorInvalidValue;
+    case 0: launch_mode<F, T, 0>(a, L, s); break;
+    case kModeDebug: launch_mode<F, T, kModeDebug>(a, L, s); break;
+    case kModeDensGlobal: launch_mode<F, T, kModeDensGlobal>(a, L, s); break;
+    case kModeDebug | kModeDensGlobal: launch_mode<F, T, kModeDebug | kModeDensGlobal>(a, L, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 size_t step_static_lds() {
   hipFuncAttributes fa;
-  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_step<double, kModeDensLds | kModeCur>)) != hipSuccess)
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_step<double, kMaxSub, kModeDebug>)) != hipSuccess)
     return 8192;
   return fa.sharedSizeBytes;
 }
 
-template <typename F, int MODE>
+template <typename F, int T>
 static hipError_t raise_lds(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<F, MODE>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipSuccess;
+  for (const void* f : {reinterpret_cast<const void*>(&k_step<F, T, 0>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeDebug>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeDensGlobal>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeDebug | kModeDensGlobal>)})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {
-  hipError_t e = hipSuccess;
-#define PIC_RAISE(m)                                         \
-  if (e == hipSuccess) e = raise_lds<float, m>(bytes);       \
-  if (e == hipSuccess) e = raise_lds<double, m>(bytes);
-  PIC_RAISE(0) PIC_RAISE(1) PIC_RAISE(2) PIC_RAISE(3) PIC_RAISE(4) PIC_RAISE(5)
-  PIC_RAISE(8) PIC_RAISE(9) PIC_RAISE(10) PIC_RAISE(11) PIC_RAISE(12) PIC_RAISE(13)
-#undef PIC_RAISE
+  hipError_t e = raise_lds<float, 1>(bytes);
+  if (e == hipSuccess) e = raise_lds<float, 2>(bytes);
+  if (e == hipSuccess) e = raise_lds<double, 1>(bytes);
+  if (e == hipSuccess) e = raise_lds<double, 2>(bytes);
   return e;
 }
 
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
-  const int mode = (a.debug ? kModeDebug : 0) |
-                   (a.dens_on ? (a.dens_lds ? kModeDensLds : kModeDensGlobal) : 0) |
-                   (a.cur_on ? kModeCur : 0);
-  return fp64 ? launch_prec<double>(a, mode, L, s) : launch_prec<float>(a, mode, L, s);
+  const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
+  const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0);
+  if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
+  hipError_t e;
+  if (a.n_sub == 2)
+    e = fp64 ? launch_prec<double, 2>(a, mode, L, s) : launch_prec<float, 2>(a, mode, L, s);
+  else
+    e = fp64 ? launch_prec<double, 1>(a, mode, L, s) : launch_prec<float, 1>(a, mode, L, s);
+  if (L.ev[1]) (void)hipEventRecord(L.ev[1], s);
+  return e;
 }
 
 hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s) {

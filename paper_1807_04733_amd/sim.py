@@ -160,11 +160,12 @@ class PicSim:
         _abi.check(self.lib.pic_time_kernels(self.handle, 1 if enable else 0))
 
     def kernel_times(self) -> np.ndarray:
-        """Rows (ms of the step launch, ms of the compaction after it, carriers whose step
-        took the common path, carriers that took the general path) of the timed steps."""
+        """Rows per timed launch: ms of the step launch, ms of the compaction after it,
+        carrier-steps on the common path, carrier-steps on the general path, first step,
+        number of steps."""
         n = C.c_int32(0)
         _abi.check(self.lib.pic_kernel_times(self.handle, None, 0, C.byref(n)))
-        out = np.zeros((max(n.value, 1), 4), dtype=np.float64)
+        out = np.zeros((max(n.value, 1), 6), dtype=np.float64)
         _abi.check(self.lib.pic_kernel_times(
             self.handle, out.ctypes.data_as(C.POINTER(C.c_double)), n.value, C.byref(n)))
         return out[:n.value]

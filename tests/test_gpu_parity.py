@@ -124,9 +124,12 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
     ref = oracle_mod.run(prob)
     for tuning in ({"block": 64, "grid": 7, "compact_every": 0, "z_every": 1},
                    {"block": 128, "grid": 1000, "compact_every": 1, "compact_frac": 0.0,
-                    "z_every": 8},
+                    "z_every": 8, "sub_steps": 2},
                    {"block": 256, "grid": 64, "compact_every": 5, "use_graph": 0, "z_every": 3},
-                   {"block": 512, "grid": 300, "compact_every": 3, "z_every": 5}):
+                   {"block": 512, "grid": 300, "compact_every": 3, "z_every": 5,
+                    "sub_steps": 2},
+                   {"block": 256, "grid": 2000, "compact_every": 2, "z_every": 2,
+                    "sub_steps": 2, "use_graph": 0}):
         from paper_1807_04733_amd import PicSim
         _say(f"[parity] launch shape {tuning}")
         sim = PicSim(prob, slab_primaries=1000, tuning=tuning)
@@ -139,6 +142,19 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
         assert np.array_equal(dens[0], ref.dens[0])
         assert np.array_equal(cur[0], ref.cur[0])
         assert np.array_equal(cnt, ref.counters)
+
+
+@pytest.mark.parametrize("cfg", ["valve", "multilayer"])
+def test_two_step_launches_records(torch_gpu, oracle_mod, cfg):
+    """Two steps per launch (the common path from registers, the general path per
+    sub-step): per-particle records and bins equal the oracle's."""
+    if cfg == "valve":
+        prob = W.config1(parallel=False, n_primaries=5000, n_steps=121)
+    else:
+        prob = W.config4(n_instances=2, primaries_per_instance=1200, n_steps=251)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=700,
+                        tuning={"sub_steps": 2, "z_every": 4})
+    assert_parity(dev, ref, prob)
 
 
 def test_capacity_overflow_is_reported(torch_gpu):
