@@ -259,9 +259,9 @@ def summarize_pmc(path: str, last: int):
         name[d] = r["Kernel_Name"]
     steps = sorted(d for d in per if "k_step" in name[d])
     sel = steps[-last:] if last else steps
-    counters = sorted({c for d in sel for c in per[d]})
+    counters = sorted({c for d in (sel or per) for c in per[d]})
     print(f"step-kernel dispatches averaged: {len(sel)} (of {len(steps)})")
-    for c in counters:
+    for c in counters if sel else []:
         print(f"  {c}: {sum(per[d][c] for d in sel) / len(sel):.6g} per dispatch")
     for k in sorted(set(name.values())):
         if "k_step" in k:
