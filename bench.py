@@ -219,11 +219,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_hbm_traffic.md
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernel's code: its source files with // comments and blank lines
+    removed, so that a comment edit does not disown a counter summary."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        for line in open(os.path.join(ROOT, f), encoding="utf-8"):
+            code = re.sub(r"//.*", "", line).rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

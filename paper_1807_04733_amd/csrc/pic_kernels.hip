@@ -1,8 +1,9 @@
 // Device kernels of the hot-electron particle-in-cell step for gfx950 (CDNA4, wave64).
 //
-// One launch of k_step advances every carrier of every instance by one step of the
-// Strang splitting of arXiv:1807.04733 Eq. (15):
-//   Source(dt/2)     primaries scheduled for this step are created in registers (Eq. 17)
+// One launch of k_step advances every carrier of every instance by one or two steps of
+// the Strang splitting of arXiv:1807.04733 Eq. (15):
+//   Source(dt/2)     primaries scheduled for the step are appended with their initial
+//                    state (Eq. 17)
 //   Transport(dt/2)  straight flight, vacuum reflection, stochastic interfaces (Eq. 18)
 //   Scattering(dt)   Monte-Carlo event with p = 1 - exp(-dt/tau_eff) (Eq. 2, Sec. III.A):
 //                    elastic (Eq. 8) or inelastic with an energy-conserving secondary
@@ -10,10 +11,11 @@
 //   Transport(dt/2)  for the survivor and the newborn
 //   deposit          density and v*cos(theta) moments (Eqs. 16, 23) into LDS histograms
 //
-// Data layout: structure-of-arrays particle state streamed once per step (z, cos(theta),
-// energy, uid, flags), partitioned into slabs that each belong to one instance.  A slab
-// is processed by one workgroup per step, which appends newborns behind the slab's tail
-// with a wave ballot + one LDS atomic per wave (no global atomics on the append path).
+// Data layout: structure-of-arrays particle state streamed once per launch (z,
+// cos(theta), energy, uid, flags), partitioned into slabs that each belong to one
+// instance.  A slab is processed by one workgroup per launch, which appends newborns
+// behind the slab's tail with a wave ballot + one LDS atomic per wave (no global atomics
+// on the append path).
 // Histograms are privatised per workgroup in LDS and merged into the int64 bins with
 // global atomics only for non-zero entries.  All decisions use binary64 arithmetic in
 // the order written here; the file is built with -ffp-contract=off.
