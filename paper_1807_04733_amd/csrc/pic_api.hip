@@ -153,7 +153,7 @@ Plan make_plan(const pic_config* c) {
     const double f = default_capacity(c, I);
     int64_t cap = (int64_t)std::ceil((double)per * f) + 64;
     cap = (cap + 63) & ~int64_t(63);
-    if (cap > (int64_t)1 << 30) cap = (int64_t)1 << 30;
+    if (cap > (int64_t)1 << 28) cap = (int64_t)1 << 28;  // 32-bit byte offsets inside a slab
     p.n_slabs_of.push_back((int32_t)S);
     p.slab0_of.push_back((int32_t)p.slab_inst.size());
     for (int64_t k = 0; k < S; ++k) {

@@ -125,6 +125,14 @@ struct SlabPtrs {
   uint64_t* ev;
 };
 
+// Element i of a slab array, addressed with a 32-bit byte offset from the slab's base
+// (a slab holds fewer than 2^28 slots), so that the access can use the scalar base + vector
+// offset form of global memory instructions.
+template <typename T>
+__device__ __forceinline__ T& at(T* base, uint32_t i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 struct LaneCounts {
   uint32_t dep, tr, ri, rs;
 };
@@ -274,8 +282,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           lc[J].dep += 1;
           n_fast[J] += 1;
           if (a.sub_z_write[J]) {
-            sp.z[slot] = (F)zs;
-            if ((fl >> kStampShift) & kStampMask) sp.fl[slot] = fl & ~(kStampMask << kStampShift);
+            at(sp.z, slot) = (F)zs;
+            if ((fl >> kStampShift) & kStampMask) at(sp.fl, slot) = fl & ~(kStampMask << kStampShift);
           }
         }
       }
@@ -404,23 +412,23 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           slot = pos;
           if ((int)pos < cap) {
             placed = true;
-            sp.z[pos] = (F)z;
-            sp.mu[pos] = (F)mu;
-            sp.E[pos] = E;
-            sp.uid[pos] = (uint64_t)lo | ((uint64_t)hi << 32);
-            sp.fl[pos] = fl;
-            if (DEBUG) sp.ev[pos] = evp;
+            at(sp.z, pos) = (F)z;
+            at(sp.mu, pos) = (F)mu;
+            at(sp.E, pos) = E;
+            at(sp.uid, pos) = (uint64_t)lo | ((uint64_t)hi << 32);
+            at(sp.fl, pos) = fl;
+            if (DEBUG) at(sp.ev, pos) = evp;
           } else {
             atomicOr(a.status, kStOverflow);
           }
         }
       }
       if (from_soa && alive0) {
-        sp.z[gi] = (F)z;
-        if (dirty & 1u) sp.mu[gi] = (F)mu;
-        if (dirty & 2u) sp.E[gi] = E;
-        if (dirty & 4u) sp.fl[gi] = fl;
-        if (DEBUG) sp.ev[gi] = evp;
+        at(sp.z, gi) = (F)z;
+        if (dirty & 1u) at(sp.mu, gi) = (F)mu;
+        if (dirty & 2u) at(sp.E, gi) = E;
+        if (dirty & 4u) at(sp.fl, gi) = fl;
+        if (DEBUG) at(sp.ev, gi) = evp;
       }
       const uint64_t md = __ballot(died);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
@@ -475,12 +483,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         pos = (uint32_t)(tail0 + off + prefix_count(m));
         if ((int)pos < cap) {
           placed = true;
-          sp.z[pos] = (F)cz;
-          sp.mu[pos] = (F)cmu;
-          sp.E[pos] = cE;
-          sp.uid[pos] = (uint64_t)lo | ((uint64_t)lin << 32);
-          sp.fl[pos] = cfl;
-          if (DEBUG) sp.ev[pos] = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
+          at(sp.z, pos) = (F)cz;
+          at(sp.mu, pos) = (F)cmu;
+          at(sp.E, pos) = cE;
+          at(sp.uid, pos) = (uint64_t)lo | ((uint64_t)lin << 32);
+          at(sp.fl, pos) = cfl;
+          if (DEBUG) at(sp.ev, pos) = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
         } else {
           atomicOr(a.status, kStOverflow);
         }
@@ -499,14 +507,14 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       wave_sync();
       fl = kDead;
       if (act) {
-        fl = sp.fl[g];
-        z = (double)sp.z[g];
-        mu = (double)sp.mu[g];
-        E = sp.E[g];
-        const uint64_t u = sp.uid[g];
+        fl = at(sp.fl, g);
+        z = (double)at(sp.z, g);
+        mu = (double)at(sp.mu, g);
+        E = at(sp.E, g);
+        const uint64_t u = at(sp.uid, g);
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
-        if (DEBUG) evp = sp.ev[g];
+        if (DEBUG) evp = at(sp.ev, g);
         const int d = phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
           const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
@@ -574,12 +582,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                             ((uint32_t)a.sub_z_phase[J] << kStampShift);
         if ((int)pos < cap) {
           placed = true;
-          sp.z[pos] = (F)z;
-          sp.mu[pos] = (F)mu;
-          sp.E[pos] = E;
-          sp.uid[pos] = (uint64_t)root;
-          sp.fl[pos] = fl;
-          if (DEBUG) sp.ev[pos] = 0;
+          at(sp.z, pos) = (F)z;
+          at(sp.mu, pos) = (F)mu;
+          at(sp.E, pos) = E;
+          at(sp.uid, pos) = (uint64_t)root;
+          at(sp.fl, pos) = fl;
+          if (DEBUG) at(sp.ev, pos) = 0;
         } else {
           atomicOr(a.status, kStOverflow);
         }
@@ -596,11 +604,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     auto fetch = [&](int t) __attribute__((always_inline)) {
       if (t < tail0) {
         const uint32_t g = (uint32_t)t;
-        nfl = sp.fl[g];
-        nz = sp.z[g];
-        nmu = sp.mu[g];
-        nE = sp.E[g];
-        nu = sp.uid[g];
+        nfl = at(sp.fl, g);
+        nz = at(sp.z, g);
+        nmu = at(sp.mu, g);
+        nE = at(sp.E, g);
+        nu = at(sp.uid, g);
       } else {
         nfl = kDead;
       }
@@ -656,8 +664,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
             }
           }
           if (left_at < 0 && a.sub_z_write[T - 1]) {
-            sp.z[gi] = (F)z;
-            if (st) sp.fl[gi] = rfl & ~(kStampMask << kStampShift);
+            at(sp.z, gi) = (F)z;
+            if (st) at(sp.fl, gi) = rfl & ~(kStampMask << kStampShift);
           }
         }
         push(Sub<0>{}, left_at == 0, gi);
