@@ -72,6 +72,7 @@ class _Output(C.Structure):
         ("rec_layer", C.POINTER(C.c_int32)), ("rec_spin", C.POINTER(C.c_int32)),
         ("rec_gen", C.POINTER(C.c_int32)), ("rec_dead", C.POINTER(C.c_int32)),
         ("rec_inst", C.POINTER(C.c_int32)), ("rec_ev", C.POINTER(C.c_int32)),
+        ("gen", C.POINTER(C.c_uint64)),
         ("g_dens", C.POINTER(C.c_double)), ("g_cur", C.POINTER(C.c_double)),
         ("grad", C.POINTER(C.c_double)), ("grad_per_tree", C.c_int32),
     ]
@@ -115,6 +116,7 @@ class OracleResult:
     counters: np.ndarray  # (n_steps, NCOUNTERS) int64
     records: Optional[dict] = None
     grad: Optional[np.ndarray] = None
+    gen: Optional[list] = None   # per instance, shape problem.gen_shape(i), uint64 sums
 
     def cur_float(self, i: int) -> np.ndarray:
         return self.cur[i].astype(np.float64) * 2.0 ** -32
@@ -122,16 +124,19 @@ class OracleResult:
 
 def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
         root_range=None, n_threads: int = 0, g_dens=None, g_cur=None,
-        grad_per_tree: bool = False) -> OracleResult:
+        grad_per_tree: bool = False, gen: Optional[bool] = None) -> OracleResult:
     """Simulate `problem` (a workloads.Problem) on the CPU.
 
     root_range=(lo, hi) restricts every instance to its local roots lo..hi-1 (trees are
     independent, so this is exactly the sub-population of a full run).  g_dens / g_cur
     (lists of arrays shaped like the bins) switch on the likelihood-ratio gradient of
     sum(g_dens*dens) + sum(g_cur*cur_float) with respect to (ln tau0 per channel, T table
-    entries).
+    entries).  gen (default: problem.gen_moment) also returns the generation moment: the
+    sum of the generation labels per (density slot, depth, spin).
     """
     lib = _load()
+    if gen is None:
+        gen = bool(getattr(problem, "gen_moment", False))
     keep = []
 
     def arr(a, dt):
@@ -190,6 +195,10 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
     O.dens = _ptr(dens, C.c_uint64)
     O.cur = _ptr(cur, C.c_int64)
     O.counters = _ptr(counters, C.c_int64)
+    ng = [int(np.prod(problem.gen_shape(i))) for i in range(len(problem.instances))]
+    gen_arr = np.zeros(sum(ng), np.uint64) if gen else None
+    if gen:
+        O.gen = _ptr(gen_arr, C.c_uint64)
     rec = None
     if records:
         if rec_cap is None:
@@ -238,7 +247,13 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
         out_c.append(cur[oc:oc + nc[i]].reshape(problem.cur_shape(i)))
         od += nd[i]
         oc += nc[i]
+    out_g = None
+    if gen:
+        out_g, og = [], 0
+        for i in range(len(problem.instances)):
+            out_g.append(gen_arr[og:og + ng[i]].reshape(problem.gen_shape(i)))
+            og += ng[i]
     if rec is not None:
         n = O.n_rec
         rec = {k: v[:n] for k, v in rec.items()}
-    return OracleResult(out_d, out_c, counters, rec, grad)
+    return OracleResult(out_d, out_c, counters, rec, grad, out_g)

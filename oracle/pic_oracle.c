@@ -116,7 +116,7 @@ typedef struct {
   orc_output* O;
   int inst_id;
   const orc_instance* I;
-  int64_t dens_off, cur_off;
+  int64_t dens_off, cur_off, gen_off;
   int K;                    /* gradient length, 0 if off */
   double* grad;             /* thread-local accumulator */
   double* tree_score;       /* per-tree mode: sum of scores of the current tree */
@@ -316,6 +316,13 @@ static void deposit(worker* W, particle* p, int n) {
 #pragma omp atomic
     W->O->dens[idx] += 1;
     if (W->K && W->O->g_dens) g += W->O->g_dens[idx];
+    if (W->O->gen) {
+      /* mean generation map of Sec. V (Figs. 5, 7): the sum of the labels per cell, to be
+       * divided by the cell's count */
+      const int64_t gi = W->gen_off + ((int64_t)(n / P->dens_stride) * I->nz + zb) * 2 + p->spin;
+#pragma omp atomic
+      W->O->gen[gi] += (uint64_t)p->gen;
+    }
   }
   if (n % P->cur_stride == 0) {
     const double vm = speed(I, p->layer, p->spin) * p->mu;
@@ -446,16 +453,19 @@ int orc_run(const orc_problem* P, orc_output* O) {
   const int NI = P->n_instances;
   int64_t* dens_off = (int64_t*)calloc((size_t)NI, sizeof(int64_t));
   int64_t* cur_off = (int64_t*)calloc((size_t)NI, sizeof(int64_t));
+  int64_t* gen_off = (int64_t*)calloc((size_t)NI, sizeof(int64_t));
   int64_t* job_start = (int64_t*)calloc((size_t)NI + 1, sizeof(int64_t));
   const int nds = (P->n_steps + P->dens_stride - 1) / P->dens_stride;
   const int ncs = (P->n_steps + P->cur_stride - 1) / P->cur_stride;
-  int64_t d = 0, c = 0;
+  int64_t d = 0, c = 0, gsum = 0;
   for (int i = 0; i < NI; ++i) {
     const orc_instance* I = &P->inst[i];
     dens_off[i] = d;
     cur_off[i] = c;
+    gen_off[i] = gsum;
     d += (int64_t)nds * I->nz * P->n_ebins * 2;
     c += (int64_t)ncs * I->nz * 2;
+    gsum += (int64_t)nds * I->nz * 2;
     int64_t tot = 0;
     for (int n = 0; n < P->n_steps; ++n) tot += I->sched[n];
     int64_t lo = P->root_lo > 0 ? P->root_lo : 0;
@@ -502,6 +512,7 @@ int orc_run(const orc_problem* P, orc_output* O) {
         W.I = I;
         W.dens_off = dens_off[i];
         W.cur_off = cur_off[i];
+        W.gen_off = gen_off[i];
       }
       const int64_t lo = P->root_lo > 0 ? P->root_lo : 0;
       const int64_t j = lo + (job - job_start[i]);
@@ -524,6 +535,7 @@ int orc_run(const orc_problem* P, orc_output* O) {
   }
   free(dens_off);
   free(cur_off);
+  free(gen_off);
   free(job_start);
   return error;
 }

@@ -75,6 +75,10 @@ typedef struct {
   int32_t*  rec_dead;         /* step of absorption, -1 if alive at the end */
   int32_t*  rec_inst;
   int32_t*  rec_ev;           /* [4] per record: events, transmissions, reflections, spawns */
+  /* optional generation moment (NULL to skip): sum of the generation label (1: primary,
+   * each secondary its parent's + 1) per (density slot, depth, spin), layout
+   * [n_dslots][nz][2] per instance, instances concatenated; taken with the density */
+  uint64_t* gen;
   /* optional likelihood-ratio gradient (NULL to skip); see orc_run's gradient section */
   const double* g_dens;       /* same layout as dens */
   const double* g_cur;        /* same layout as cur (per unit of nm/fs) */

@@ -129,6 +129,7 @@ class Problem:
     dens_stride: int = 1
     cur_stride: int = 1
     name: str = ""
+    gen_moment: bool = False      # also bin the generation label (with the density)
 
     @property
     def n_ebins(self) -> int:
@@ -147,6 +148,9 @@ class Problem:
 
     def cur_shape(self, i: int):
         return (self.n_cslots, self.instances[i].nz, 2)
+
+    def gen_shape(self, i: int):
+        return (self.n_dslots, self.instances[i].nz, 2)
 
     @property
     def n_primaries(self) -> int:
