@@ -63,6 +63,7 @@ typedef enum {
 #define PIC_F_STATE_FP64   1u  /* z and cos(theta) stored as binary64 (else binary32) */
 #define PIC_F_SECONDARIES  2u  /* inelastic events lift a secondary carrier (Eq. 6-7) */
 #define PIC_F_DEBUG        4u  /* keep per-particle event counts (see pic_layout) */
+#define PIC_F_GEN_MOMENT   8u  /* also bin the generation label with the density */
 
 /* per-step counters returned by pic_counters(), [n_steps][PIC_NCOUNTERS] */
 enum {
@@ -182,6 +183,14 @@ pic_status pic_compact(pic_ctx* ctx);
  * counts and cur_out [sum_i n_cslots*nz_i*2] sum of v*cos(theta) in nm/fs; instances are
  * concatenated in order.  Device pointers (either may be NULL).  Enqueued, async. */
 pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
+
+/* Generation moment (context created with PIC_F_GEN_MOMENT): the sum of the generation
+ * labels (1: primary, each secondary its parent's + 1, capped at 255) of the carriers
+ * deposited in each density cell, per (density slot, depth, spin): gen_out
+ * [sum_i n_dslots*nz_i*2], binary64 (exact integers), instances concatenated; divided by
+ * the energy-summed density it is the mean generation map of Sec. V.  Device pointer.
+ * Enqueued, async.  PIC_ESTATE without the flag. */
+pic_status pic_generations(pic_ctx* ctx, double* gen_out);
 
 /* Likelihood-ratio adjoint: gradient of sum(g_dens*dens) + sum(g_cur*cur) with respect
  * to ln tau0 per channel and every transmission-table entry, written to grad_out

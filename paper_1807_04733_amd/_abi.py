@@ -16,6 +16,7 @@ MAX_EBINS = 128
 F_STATE_FP64 = 1
 F_SECONDARIES = 2
 F_DEBUG = 4
+F_GEN_MOMENT = 8
 
 COUNTER_NAMES = ("injected", "ev_ee", "ev_el", "spawned", "absorbed", "sec_absorbed",
                  "transmit", "refl_if", "refl_surf", "alive", "e_absorbed")
@@ -27,6 +28,7 @@ STATUS = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ENOMEM", 3: "PIC_ECAPACITY", 4: 
 EXPORTS = ("pic_workspace_size", "pic_init", "pic_inject", "pic_step", "pic_compact", "pic_deposit",
            "pic_backward", "pic_counters", "pic_reset", "pic_set_tuning", "pic_get_tuning",
            "pic_layout_of", "pic_autotune", "pic_time_kernels", "pic_kernel_times",
+           "pic_generations",
            "pic_destroy", "pic_last_error")
 
 
@@ -112,6 +114,7 @@ def load():
         "pic_layout_of": ([vp, P(PicLayout)], C.c_int),
         "pic_autotune": ([vp, C.c_int32, P(PicTuning)], C.c_int),
         "pic_time_kernels": ([vp, C.c_int32], C.c_int),
+        "pic_generations": ([vp, vp], C.c_int),
         "pic_kernel_times": ([vp, P(C.c_double), C.c_int32, P(C.c_int32)], C.c_int),
         "pic_destroy": ([vp], None),
         "pic_last_error": ([], C.c_char_p),

@@ -42,15 +42,15 @@ struct Plan {
   std::vector<int32_t> slab_inst, slab_k, slab_cap;
   std::vector<int64_t> slab_base;
   std::vector<int32_t> n_slabs_of, slab0_of;
-  std::vector<int64_t> dens_off, cur_off;
-  int64_t capacity = 0, dens_len = 0, cur_len = 0;
+  std::vector<int64_t> dens_off, cur_off, gen_off;
+  int64_t capacity = 0, dens_len = 0, cur_len = 0, gen_len = 0;
   int n_dslots = 0, n_cslots = 0, state_bytes = 4;
   bool debug = false;
   // byte offsets inside the workspace
   int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
   int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
   int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
-  int64_t off_stats;
+  int64_t off_stats, off_gen = -1;
   int64_t off_grad = -1, off_S = -1, off_r = -1, off_R = -1;
   int K = 0;
   int64_t n_roots = 0;
@@ -165,8 +165,10 @@ Plan make_plan(const pic_config* c) {
     }
     p.dens_off.push_back(p.dens_len);
     p.cur_off.push_back(p.cur_len);
+    p.gen_off.push_back(p.gen_len);
     p.dens_len += (int64_t)p.n_dslots * I.nz * c->n_ebins * 2;
     p.cur_len += (int64_t)p.n_cslots * I.nz * 2;
+    if (c->flags & PIC_F_GEN_MOMENT) p.gen_len += (int64_t)p.n_dslots * I.nz * 2;
   }
   const int64_t C = p.capacity, NS = (int64_t)p.slab_inst.size(), NI = c->n_instances;
   int64_t o = 0;
@@ -196,6 +198,7 @@ Plan make_plan(const pic_config* c) {
   p.off_queue = take((int64_t)c->n_steps * 4 * 2);
   p.off_status = take(64);
   p.off_stats = take((int64_t)c->n_steps * 2 * 8);
+  if (c->flags & PIC_F_GEN_MOMENT) p.off_gen = take(p.gen_len * 8);
   if (c->adjoint) {
     const pic_instance& I0 = c->inst[0];
     p.K = I0.n_channels + I0.n_ttables * I0.t_entries;
@@ -276,6 +279,12 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
     if (a) a->lds_cur_at[j] = u ? (int32_t)off : -1;
     if (u) off = (off + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
   }
+  // generation-moment slices (u32 per (z, spin)) beside the density slices in LDS
+  for (int j = 0; j < kMaxSub; ++j) {
+    const bool g = j < n_sub && dens_on[j] && c->dens_lds && c->plan.off_gen >= 0;
+    if (a) a->lds_gen_at[j] = g ? (int32_t)off : -1;
+    if (g) off = (off + (size_t)c->lds_cur_words * 4 + 15) & ~(size_t)15;
+  }
   if (a) {
     a->lds_q_at = (int32_t)off;
     a->lds_q_bytes = (int32_t)step_queue_bytes(n_sub);
@@ -331,6 +340,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.queue = c->at<int32_t>(p.off_queue);
   a.status = c->at<uint32_t>(p.off_status);
   a.stats = c->at<unsigned long long>(p.off_stats);
+  a.gen = c->at<uint64_t>(p.off_gen);
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
   a.n_ebins = c->cfg.n_ebins;
@@ -486,6 +496,7 @@ pic_status upload_tables(pic_ctx* c) {
     D.root_offset = I.root_offset;
     D.dens_off = p.dens_off[i];
     D.cur_off = p.cur_off[i];
+    D.gen_off = p.gen_off[i];
     for (int k = 0; k < I.n_layers - 1; ++k)
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s) D.tt[k][d][s] = (uint8_t)I.tt_of[k][d][s];
@@ -524,6 +535,7 @@ pic_status clear_state(pic_ctx* c) {
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_queue), (int64_t)c->cfg.n_steps * 2, 0, c->stream));
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_status), 16, 0, c->stream));
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_stats), (int64_t)c->cfg.n_steps * 4, 0, c->stream));
+  if (p.off_gen >= 0) HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_gen), p.gen_len * 2, 0, c->stream));
   c->step = 0;
   return PIC_OK;
 }
@@ -663,6 +675,14 @@ pic_status pic_deposit(pic_ctx* c, double* dens_out, double* cur_out) {
   HIP_TRY(launch_convert(c->at<uint64_t>(c->plan.off_dens), dens_out ? c->plan.dens_len : 0,
                          c->at<int64_t>(c->plan.off_cur), cur_out ? c->plan.cur_len : 0, dens_out,
                          cur_out, c->stream));
+  return PIC_OK;
+}
+
+pic_status pic_generations(pic_ctx* c, double* gen_out) {
+  if (!c || !gen_out) return fail(PIC_EINVAL, "null argument");
+  if (c->plan.off_gen < 0) return fail(PIC_ESTATE, "context created without PIC_F_GEN_MOMENT");
+  HIP_TRY(launch_convert(c->at<uint64_t>(c->plan.off_gen), c->plan.gen_len, nullptr, 0, gen_out,
+                         nullptr, c->stream));
   return PIC_OK;
 }
 

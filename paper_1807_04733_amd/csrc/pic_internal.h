@@ -53,6 +53,7 @@ struct alignas(32) DevInst {
   int32_t n_layers, t_entries, nz, n_slabs;
   uint64_t root_offset;
   int64_t dens_off, cur_off;   // element offsets of this instance in the global bins
+  int64_t gen_off;             // ... in the generation-moment bins
   int32_t slab0, pad1;
   uint8_t tt[kMaxL - 1][2][2]; // transmission table per (interface, direction, spin)
   uint8_t chi[kMaxL][2];       // channel index per (layer, spin) (adjoint parameter slot)
@@ -110,6 +111,10 @@ struct StepArgs {
   int32_t sub_z_phase[kMaxSub], sub_z_write[kMaxSub];
   int32_t lds_dens_at[kMaxSub], lds_cur_at[kMaxSub];
   int32_t lds_q_at, lds_q_bytes;
+  // generation moment: sum of generation labels per (density slot, z, spin), taken with
+  // the density (LDS slice per sub-step at lds_gen_at, u32), or null
+  uint64_t* gen;
+  int32_t lds_gen_at[kMaxSub];
 };
 
 struct AdjArgs {

@@ -54,6 +54,15 @@ __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uns
     } else {
       atomicAdd((uint32_t*)(dyn + a.lds_dens_at[J]) + idx, 1u);
     }
+    if (a.gen) {  // generation label, summed per (z, spin)
+      const uint32_t gl = (fl >> kGenShift) & kGenMask;
+      if (MODE & kModeDensGlobal) {
+        const int64_t g = I.gen_off + ((int64_t)a.sub_dens_slot[J] * I.nz + zb) * 2 + s;
+        atomicAdd((unsigned long long*)&a.gen[g], (unsigned long long)gl);
+      } else {
+        atomicAdd((uint32_t*)(dyn + a.lds_gen_at[J]) + zb * 2 + s, gl);
+      }
+    }
   }
   if (a.sub_cur_on[J]) {
     const double vm = v * mu;
@@ -79,6 +88,19 @@ __device__ void flush_bins(const StepArgs& a, const DevInst& I, unsigned char* d
       if (v) {
         atomicAdd(&g[b], (unsigned long long)v);
         s_dens[b] = 0;
+      }
+    }
+    if (a.gen) {
+      uint32_t* s_gen = (uint32_t*)(dyn + a.lds_gen_at[J]);
+      const int m = I.nz * 2;
+      unsigned long long* gg =
+          (unsigned long long*)(a.gen + I.gen_off + (int64_t)a.sub_dens_slot[J] * m);
+      for (int b = threadIdx.x; b < m; b += blockDim.x) {
+        const uint32_t v = s_gen[b];
+        if (v) {
+          atomicAdd(&gg[b], (unsigned long long)v);
+          s_gen[b] = 0;
+        }
       }
     }
   }

@@ -66,6 +66,8 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
         flags |= _abi.F_SECONDARIES
     if debug:
         flags |= _abi.F_DEBUG
+    if getattr(problem, "gen_moment", False):
+        flags |= _abi.F_GEN_MOMENT
     cfg.flags = flags
     if problem.n_ebins > _abi.MAX_EBINS:
         raise ValueError("too many energy bins")
@@ -231,6 +233,25 @@ class PicSim:
             od += nd
             oc += nc
         return dens, cur
+
+    def generations(self):
+        """Generation moment per instance (device tensors shaped problem.gen_shape(i)): the
+        sum of the generation labels of the carriers in each density cell (the problem
+        must have gen_moment set)."""
+        import torch
+
+        shapes = [self.problem.gen_shape(i) for i in range(len(self.problem.instances))]
+        n = sum(int(np.prod(sh)) for sh in shapes)
+        with torch.cuda.stream(self.stream):
+            g = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+            _abi.check(self.lib.pic_generations(self.handle, C.c_void_p(g.data_ptr())))
+        self.stream.synchronize()
+        out, o = [], 0
+        for sh in shapes:
+            m = int(np.prod(sh))
+            out.append(g[o:o + m].view(sh))
+            o += m
+        return out
 
     def int_bins(self):
         """The raw integer bins (uint64 counts, int64 2^-32 nm/fs) as host arrays."""

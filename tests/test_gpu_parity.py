@@ -47,9 +47,10 @@ def run_both(prob, oracle_mod, *, debug=True, tuning=None, slab_primaries=0, rec
     fd = [x.cpu().numpy() for x in fd]
     fc = [x.cpu().numpy() for x in fc]
     parts = sim.particles() if records else None
+    gen = [x.cpu().numpy() for x in sim.generations()] if prob.gen_moment else None
     sim.close()
     ref = oracle_mod.run(prob, records=records)
-    return dict(cnt=cnt, dens=dens, cur=cur, fd=fd, fc=fc, parts=parts), ref
+    return dict(cnt=cnt, dens=dens, cur=cur, fd=fd, fc=fc, parts=parts, gen=gen), ref
 
 
 def assert_parity(dev, ref, prob, *, exact_bins=True):
@@ -66,6 +67,8 @@ def assert_parity(dev, ref, prob, *, exact_bins=True):
         if exact_bins:
             assert np.array_equal(dev["dens"][i], ref.dens[i])
             assert np.array_equal(dev["cur"][i], ref.cur[i])
+        if dev["gen"] is not None:
+            assert np.array_equal(dev["gen"][i], ref.gen[i].astype(np.float64))
     if exact_bins:
         assert np.array_equal(dev["cnt"], ref.counters)
 
@@ -94,6 +97,7 @@ def test_elastic_and_constant_tau(torch_gpu, oracle_mod):
 
 def test_batched_instances(torch_gpu, oracle_mod):
     prob = W.config2(n_instances=6, n_steps=70, prim_lo=50, prim_hi=3000)
+    prob.gen_moment = True
     dev, ref = run_both(prob, oracle_mod, slab_primaries=512)
     assert_parity(dev, ref, prob)
 
@@ -152,6 +156,7 @@ def test_two_step_launches_records(torch_gpu, oracle_mod, cfg):
         prob = W.config1(parallel=False, n_primaries=5000, n_steps=121)
     else:
         prob = W.config4(n_instances=2, primaries_per_instance=1200, n_steps=251)
+    prob.gen_moment = True
     dev, ref = run_both(prob, oracle_mod, slab_primaries=700,
                         tuning={"sub_steps": 2, "z_every": 4})
     assert_parity(dev, ref, prob)
