@@ -59,6 +59,7 @@ class _Problem(C.Structure):
         ("n_ebins", C.c_int32), ("e_edges", C.POINTER(C.c_uint32)),
         ("dens_stride", C.c_int32), ("cur_stride", C.c_int32),
         ("root_lo", C.c_int64), ("root_hi", C.c_int64), ("n_threads", C.c_int32),
+        ("absorb_next", C.c_int32),
     ]
 
 
@@ -185,6 +186,7 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
     P.cur_stride = problem.cur_stride
     P.root_lo, P.root_hi = (root_range if root_range is not None else (0, -1))
     P.n_threads = n_threads
+    P.absorb_next = int(bool(getattr(problem, "absorb_next", False)))
 
     nd = [int(np.prod(problem.dens_shape(i))) for i in range(len(problem.instances))]
     nc = [int(np.prod(problem.cur_shape(i))) for i in range(len(problem.instances))]

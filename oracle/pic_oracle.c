@@ -241,6 +241,14 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
   }
   add_score(W, p, c, -x_in * exp(-x) / prob);
   p->ev[0]++;
+  if (P->absorb_next && p->E < P->e_min_fx) {
+    /* Sec. III.A: a carrier of the lowest energy bin leaves the hot population at its
+     * next scattering event (quasi-thermalised) */
+    p->dead = n;
+    count(W, n, ORC_C_ABSORBED, 1);
+    count(W, n, ORC_C_E_ABSORBED, (int64_t)p->E);
+    return 0;
+  }
   const int elastic = I->inv_tau_el[l] > 0.0 && unif(w[1]) < I->inv_tau_el[l] / rate;
   if (I->inv_tau_el[l] > 0.0) add_score(W, p, c, elastic ? x_in / x : -1.0 + x_in / x);
   /* random-k approximation: the outgoing direction is isotropic (Eq. 4) */
@@ -257,7 +265,7 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
   p->E = E1;
   int made = 0;
   if (P->secondaries) {
-    if (E2 >= P->e_min_fx) {
+    if (E2 >= P->e_min_fx || P->absorb_next) {
       uint32_t s[4];
       draw(P, p->root, p->lin, (uint32_t)n, TAG_SPAWN, s);
       *child = *p;
@@ -285,7 +293,7 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
       count(W, n, ORC_C_E_ABSORBED, (int64_t)E2);
     }
   }
-  if (E1 < P->e_min_fx) {
+  if (E1 < P->e_min_fx && !P->absorb_next) {
     p->dead = n;
     count(W, n, ORC_C_ABSORBED, 1);
     count(W, n, ORC_C_E_ABSORBED, (int64_t)E1);

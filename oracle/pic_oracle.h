@@ -55,6 +55,9 @@ typedef struct {
   int32_t dens_stride, cur_stride;
   int64_t root_lo, root_hi;   /* simulate local roots in [lo, hi) of every instance; hi<0: all */
   int32_t n_threads;          /* 0: OpenMP default */
+  int32_t absorb_next;        /* 0: a product below E_min is removed at once; 1: carriers
+                                 below E_min live on and are removed at their next
+                                 scattering event (Sec. III.A, lowest energy bin) */
 } orc_problem;
 
 typedef struct {

@@ -39,6 +39,37 @@ def test_gradient_of_cascade_closed_form(oracle_lib, per_tree):
     assert abs(m - exact) < 4 * se + 1e-3, (m, exact, se)
 
 
+@pytest.mark.parametrize("per_tree", [False, True])
+def test_gradient_with_next_scatter_removal(oracle_lib, per_tree):
+    """Removal at the next event with E_min > 0, constant tau: E[N_alive after n steps] =
+    sum_k m_k(n, p) P_k with m_k = C(n,k) (2p)^k (1-p)^(n-k) and P_k = P(prod_{i<k} U_i >=
+    x) independent of tau0, so d/d ln tau0 = sum_k m_k (k/p - (n-k)/(1-p)) P_k dp/d ln tau0
+    with dp/d ln tau0 = -x_dt e^{-x_dt}, x_dt = dt/tau0."""
+    n, dt, tau, E0, emin, N = 20, 1.0, 20.0, 1.5, 0.3, 6000
+    xd = dt / tau
+    p = -math.expm1(-xd)
+    x = emin / E0
+    lx = -math.log(x)
+    dsum = 0.0
+    for k in range(n + 1):
+        m_k = math.comb(n, k) * (2 * p) ** k * (1 - p) ** (n - k)
+        P_k = 1.0 if k <= 1 else 1.0 - x * sum(lx ** j / math.factorial(j) for j in range(k - 1))
+        dsum += m_k * (k / p - (n - k) / (1 - p)) * P_k
+    exact = dsum * (-xd * math.exp(-xd))
+
+    def one(seed):
+        prob = W.homogeneous(thickness=60.0, n_primaries=N, n_steps=n, tau0=tau, tau_exp=0,
+                             dt=dt, e_min_ev=emin, e0_ev=E0, seed=seed)
+        prob.absorb_next = True
+        gd = np.zeros(prob.dens_shape(0))
+        gd[-1] = 1.0
+        g = oracle_lib.run(prob, g_dens=[gd], grad_per_tree=per_tree).grad
+        return (g[W.AU_UP] + g[W.AU_DN]) / N
+
+    m, se = _seeds(one, 10)
+    assert abs(m - exact) < 4 * se + 1e-3, (m, exact, se)
+
+
 def test_zero_mean_score(oracle_lib):
     """Without secondaries and without absorption the number of carriers is the number
     injected whatever tau0 and T are: the gradient estimate has zero mean."""

@@ -307,6 +307,34 @@ def test_generation_moment_without_secondaries(oracle_lib):
     assert np.array_equal(res.gen[0], res.dens[0].sum(axis=2))
 
 
+def test_cascade_closed_form_next_scatter_removal(oracle_lib):
+    """Removal at the next scattering event (Sec. III.A, lowest energy bin), constant
+    lifetime: a carrier with k events in its ancestry is alive iff its energy before the
+    k-th event was at least E_min (it split there; a carrier below E_min is removed at its
+    event instead), i.e. E[N_alive] = sum_k m_k(n) P(prod_{i<k} U_i >= x)."""
+    n, dt, tau, E0, emin = 40, 1.0, 30.0, 1.5, 0.3
+    p = -math.expm1(-dt / tau)
+    x = emin / E0
+    exp = 0.0
+    lx = -math.log(x)
+    for k in range(n + 1):
+        m_k = math.comb(n, k) * (2 * p) ** k * (1 - p) ** (n - k)
+        surv = 1.0 if k <= 1 else 1.0 - x * sum(lx ** j / math.factorial(j) for j in range(k - 1))
+        exp += m_k * surv
+    prob = W.homogeneous(thickness=60.0, n_primaries=8000, n_steps=n, tau0=tau, tau_exp=0,
+                         dt=dt, e_min_ev=emin, e0_ev=E0)
+    prob.absorb_next = True
+    res = _run(oracle_lib, prob, records=True)
+    rec = res.records
+    alive = rec["dead"] < 0
+    per_root = np.bincount((rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64)[alive],
+                           minlength=8000)
+    se = per_root.std() / math.sqrt(len(per_root))
+    assert abs(per_root.mean() - exp) < 4 * se, (per_root.mean(), exp, se)
+    # the immediate-removal expectation differs by many standard errors here
+    assert abs(_alive_expectation(n, p, x) - exp) > 10 * se
+
+
 def test_cascade_energy_histogram(oracle_lib):
     """Energy spectrum of the cascade after n steps (E_min = 0): a carrier with k splits
     has energy E0*prod(U_i), density (ln(E0/E))^(k-1)/((k-1)! E0)."""
@@ -337,10 +365,13 @@ def test_cascade_energy_histogram(oracle_lib):
 
 
 # --------------------------------------------------------------------------- D, E, F
-def test_conservation_counts_energy_and_bound(oracle_lib):
+@pytest.mark.parametrize("absorb_next", [False, True])
+def test_conservation_counts_energy_and_bound(oracle_lib, absorb_next):
     """Integer conservation every step (Eq. 17), exact energy conservation of the
-    e-e events (Sec. III.A) and the per-tree alive bound floor(E0/E_min)."""
+    e-e events (Sec. III.A) and the per-tree alive bound floor(E0/E_min) (immediate
+    removal only: with removal at the next event, carriers below E_min stay alive)."""
     prob = W.config0(n_primaries=3000, n_steps=150)
+    prob.absorb_next = absorb_next
     res = _run(oracle_lib, prob, records=True)
     c = res.counters
     names = oracle_lib.COUNTER_NAMES
@@ -354,7 +385,11 @@ def test_conservation_counts_energy_and_bound(oracle_lib):
     assert e_alive + int(col["e_absorbed"].sum()) == 3000 * W.e_fx(1.5)
     roots = (rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
     per_root = np.bincount(roots[alive], minlength=3000)
-    assert per_root.max() <= W.e_fx(1.5) // prob.e_min_fx
+    if not absorb_next:
+        assert per_root.max() <= W.e_fx(1.5) // prob.e_min_fx
+    else:
+        assert col["sec_absorbed"].sum() == 0        # every secondary is created
+        assert (rec["E"][alive] < prob.e_min_fx).any()   # carriers below E_min live on
     # spawns recorded per particle add up to the spawn counter
     assert rec["ev"][:, 3].sum() == col["spawned"].sum()
     assert len(rec["uid"]) == 3000 + col["spawned"].sum()

@@ -130,6 +130,7 @@ class Problem:
     cur_stride: int = 1
     name: str = ""
     gen_moment: bool = False      # also bin the generation label (with the density)
+    absorb_next: bool = False     # below E_min: removed at the next event, not at once
 
     @property
     def n_ebins(self) -> int:
