@@ -64,6 +64,9 @@ typedef enum {
 #define PIC_F_SECONDARIES  2u  /* inelastic events lift a secondary carrier (Eq. 6-7) */
 #define PIC_F_DEBUG        4u  /* keep per-particle event counts (see pic_layout) */
 #define PIC_F_GEN_MOMENT   8u  /* also bin the generation label with the density */
+#define PIC_F_ABSORB_NEXT 16u  /* a carrier below E_min is removed at its next scattering
+                                  event (Sec. III.A, lowest energy bin) instead of at once;
+                                  every secondary is created */
 
 /* per-step counters returned by pic_counters(), [n_steps][PIC_NCOUNTERS] */
 enum {

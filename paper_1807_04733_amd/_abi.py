@@ -17,6 +17,7 @@ F_STATE_FP64 = 1
 F_SECONDARIES = 2
 F_DEBUG = 4
 F_GEN_MOMENT = 8
+F_ABSORB_NEXT = 16
 
 COUNTER_NAMES = ("injected", "ev_ee", "ev_el", "spawned", "absorbed", "sec_absorbed",
                  "transmit", "refl_if", "refl_surf", "alive", "e_absorbed")

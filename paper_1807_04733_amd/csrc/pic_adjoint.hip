@@ -267,15 +267,19 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
           ops.flush(L, fl, step, c, x_in);
           const double prob = -expm1(-x);
           if (ADJ != 2) ops.score(L, c, -x_in * exp(-x) / prob);
-          const bool elastic = itel > 0.0 && u01(w.y) < itel / rate;
-          if (ADJ != 2 && itel > 0.0) ops.score(L, c, elastic ? x_in / x : -1.0 + x_in / x);
+          // removal at the next event (lowest energy bin): no channel choice follows
+          const bool removed = a.absorb_next && E < a.e_min;
+          if (removed) died = true;
+          const bool elastic = !removed && itel > 0.0 && u01(w.y) < itel / rate;
+          if (ADJ != 2 && itel > 0.0 && !removed)
+            ops.score(L, c, elastic ? x_in / x : -1.0 + x_in / x);
           fl = with_nf(fl, step + 1);
-          mu = to_store<F>(dircos(w.z));
-          if (!elastic) {
+          if (!removed) mu = to_store<F>(dircos(w.z));
+          if (!elastic && !removed) {
             const uint32_t E1 = __umulhi(w.w, E);
             const uint32_t E2 = E - E1;
             E = E1;
-            if (a.secondaries && E2 >= a.e_min) {
+            if (a.secondaries && (E2 >= a.e_min || a.absorb_next)) {
               // the newborn: slot now, score row / return inherited, second half step
               const int cpos = append_slot(true, &s_app, tail0);
               if (cpos < cap) {
@@ -316,7 +320,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
                 atomicOr(a.status, kStOverflow);
               }
             }
-            if (E1 < a.e_min) died = true;
+            if (E1 < a.e_min && !a.absorb_next) died = true;
           }
         }
         if (!died) {

@@ -134,8 +134,10 @@ double default_capacity(const pic_config* c, const pic_instance& I) {
   if (c->e_min_fx == 0) return 32.0;
   const uint64_t e0 = std::max((uint64_t)I.src_e_lo[0] + I.src_e_span[0],
                                (uint64_t)I.src_e_lo[1] + I.src_e_span[1]);
-  // every carrier of a tree keeps at least E_min, and energy is conserved
-  return std::min<double>((double)(e0 / c->e_min_fx) + 2.0, 64.0);
+  // every carrier of a tree keeps at least E_min, and energy is conserved; with removal
+  // at the next event carriers below E_min live on as well: twice the headroom
+  const double f = (double)(e0 / c->e_min_fx) + 2.0;
+  return std::min<double>((c->flags & PIC_F_ABSORB_NEXT) ? 2.0 * f : f, 64.0);
 }
 
 Plan make_plan(const pic_config* c) {
@@ -353,6 +355,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.h = 0.5 * c->cfg.dt;
   a.tau_exp2 = c->cfg.tau_exp == 2;
   a.secondaries = (c->cfg.flags & PIC_F_SECONDARIES) != 0;
+  a.absorb_next = (c->cfg.flags & PIC_F_ABSORB_NEXT) != 0;
   a.debug = p.debug;
   a.dens_on = (n % c->cfg.dens_stride) == 0;
   a.cur_on = (n % c->cfg.cur_stride) == 0;

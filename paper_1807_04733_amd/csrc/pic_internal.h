@@ -91,6 +91,7 @@ struct StepArgs {
   uint32_t e_min;
   double dt, h;
   int32_t tau_exp2, secondaries, debug;
+  int32_t absorb_next;         // below E_min: removed at the next event (else at once)
   int32_t dens_on, cur_on;     // this step deposits density / current
   int32_t dens_slot, cur_slot;
   int32_t dens_lds;            // density privatised in LDS (else global atomics)

@@ -354,7 +354,13 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         } else {
           event = u0 < -expm1(-x);
         }
-        if (event) {
+        if (event && a.absorb_next && E < a.e_min) {
+          // a carrier of the lowest energy bin leaves the population at its next event
+          if (DEBUG) evp += 1ull;
+          died = true;
+          atomicAdd(&s_cnt[J][PIC_C_ABSORBED], 1ull);
+          atomicAdd(&s_cnt[J][PIC_C_E_ABSORBED], (unsigned long long)E);
+        } else if (event) {
           if (DEBUG) evp += 1ull;
           const bool elastic = itel > 0.0 && u01(w.y) < itel / rate;
           mu = to_store<F>(dircos(w.z));
@@ -368,7 +374,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
             E = E1;
             dirty |= 2u;
             if (a.secondaries) {
-              if (E2 >= a.e_min) {
+              // with removal at the next event every secondary is created
+              if (E2 >= a.e_min || a.absorb_next) {
                 spawn = true;
                 zmid = z;
                 flmid = fl;
@@ -379,7 +386,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                 atomicAdd(&s_cnt[J][PIC_C_E_ABSORBED], (unsigned long long)E2);
               }
             }
-            if (E1 < a.e_min) {
+            if (E1 < a.e_min && !a.absorb_next) {
               died = true;
               atomicAdd(&s_cnt[J][PIC_C_ABSORBED], 1ull);
               atomicAdd(&s_cnt[J][PIC_C_E_ABSORBED], (unsigned long long)E1);

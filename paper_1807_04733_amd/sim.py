@@ -68,6 +68,8 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
         flags |= _abi.F_DEBUG
     if getattr(problem, "gen_moment", False):
         flags |= _abi.F_GEN_MOMENT
+    if getattr(problem, "absorb_next", False):
+        flags |= _abi.F_ABSORB_NEXT
     cfg.flags = flags
     if problem.n_ebins > _abi.MAX_EBINS:
         raise ValueError("too many energy bins")

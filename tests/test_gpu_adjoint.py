@@ -66,6 +66,19 @@ def test_gradient_matches_oracle_bilayer(torch_gpu, oracle_mod, estimator):
     assert np.abs(g - ref).max() <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_gradient_matches_oracle_removal_at_next_event(torch_gpu, oracle_mod, estimator):
+    prob = W.config3(n_primaries=5000, n_steps=90)
+    prob.e_min_fx = W.e_fx(0.3)
+    prob.absorb_next = True
+    gd, gc = _random_g(prob, 3)
+    g = _gpu_grad(prob, gd, gc, estimator, slab_primaries=1000, capacity_factor=40)
+    ref = oracle_mod.run(prob, g_dens=gd, g_cur=gc, grad_per_tree=bool(estimator)).grad
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(g - ref).max() <= 1e-9 * scale
+
+
 def test_gradient_matches_oracle_batched_tables(torch_gpu, oracle_mod):
     prob = W.config4(n_instances=2, primaries_per_instance=800, n_steps=300)
     gd, gc = _random_g(prob, 2, frac=0.02)

@@ -162,6 +162,20 @@ def test_two_step_launches_records(torch_gpu, oracle_mod, cfg):
     assert_parity(dev, ref, prob)
 
 
+@pytest.mark.parametrize("sub_steps", [1, 2])
+def test_removal_at_next_event(torch_gpu, oracle_mod, sub_steps):
+    """The paper's rule for the lowest energy bin (carriers below E_min removed at their
+    next scattering event): records, bins and counters equal the oracle's."""
+    prob = W.config1(parallel=True, n_primaries=4000, n_steps=160)
+    prob.e_min_fx = W.e_fx(0.3)
+    prob.absorb_next = True
+    prob.gen_moment = True
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=900,
+                        tuning={"sub_steps": sub_steps, "z_every": 4})
+    assert_parity(dev, ref, prob)
+    assert ref.counters[:, 5].sum() == 0          # no secondary is dropped at birth
+
+
 def test_capacity_overflow_is_reported(torch_gpu):
     from paper_1807_04733_amd import PicSim, PicError
     prob = W.config0(n_primaries=2000, n_steps=100)
