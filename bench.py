@@ -190,6 +190,40 @@ def sequential_leg(prob, batched_s: float):
                 particle_steps=ps)
 
 
+def variants_leg(prob, tuning: dict):
+    """The batched workload with the physics switches of the paper's comparisons, one timed
+    run each (same launch tuning as the headline run)."""
+    import torch
+    from paper_1807_04733_amd import PicSim
+
+    out = {}
+    cases = {
+        "generation_moment": dict(gen_moment=True),
+        "removal_at_next_event": dict(absorb_next=True),
+        "elastic_30fs": dict(tau_el=30.0),
+        "transparent_interfaces": dict(transparent=True),
+        "no_secondaries": dict(secondaries=False),
+    }
+    for name, kw in cases.items():
+        sim = PicSim(W.variant(prob, **kw), device="cuda:0")
+        sim.set_tuning(**{k: v for k, v in tuning.items() if k != "use_graph"})
+        sim.step()
+        sim.counters()
+        sim.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step()
+        cnt = sim.counters()
+        dt = time.perf_counter() - t0
+        sim.close()
+        torch.cuda.empty_cache()
+        ps = particle_steps(cnt)
+        out[name] = dict(particle_steps=ps, seconds=round(dt, 4), rate=round(ps / dt, 0))
+        print(f"[bench] variant {name}: {ps / dt:.4g} particle-steps/s", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def summarize_trace(path: str):
     """Per-kernel statistics of a rocprofv3 --kernel-trace CSV (ms)."""
     import csv
@@ -298,6 +332,8 @@ def main():
                     help="primaries of the forward+adjoint leg (0: skip)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip running the batched stacks one by one")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the physics-variant runs of the batched workload")
     ap.add_argument("--summarize-pmc", default="",
                     help="print per-dispatch counter means of a rocprofv3 --pmc CSV and exit")
     ap.add_argument("--source-hash", action="store_true",
@@ -406,6 +442,9 @@ def main():
         print("[bench] running the stacks one by one", file=sys.stderr, flush=True)
         extra["sequential"] = sequential_leg(prob, wall / args.steps)
         print(f"[bench] sequential: {extra['sequential']}", file=sys.stderr, flush=True)
+    if args.workload == "batched" and not args.no_variants:
+        print("[bench] physics variants", file=sys.stderr, flush=True)
+        extra["variants"] = variants_leg(prob, extra["tuning"])
     if args.adjoint_primaries > 0:
         print("[bench] forward + adjoint leg", file=sys.stderr, flush=True)
         try:

@@ -299,6 +299,30 @@ def spin_valve(fe1: float = 15.0, au: float = 100.0, fe2: float = 15.0, parallel
     return [Layer("Fe", fe1, +1), Layer("Au", au, 0), Layer("Fe", fe2, +1 if parallel else -1)]
 
 
+def variant(problem: Problem, *, tau_el: Optional[float] = None, transparent: bool = False,
+            secondaries: Optional[bool] = None, absorb_next: Optional[bool] = None,
+            gen_moment: Optional[bool] = None) -> Problem:
+    """A copy of `problem` with the physics switches of the paper's comparisons (Sec. V):
+    an elastic channel of lifetime tau_el in every layer, transparent interfaces (T = 1),
+    secondaries on / off, removal at the next event, and the generation moment."""
+    insts = []
+    for it in problem.instances:
+        it = replace(it)
+        if tau_el is not None:
+            it.inv_tau_el = np.full(it.n_layers, 1.0 / tau_el if tau_el > 0 else 0.0)
+        if transparent:
+            it.T = np.ones_like(it.T)
+        insts.append(it)
+    out = replace(problem, instances=insts)
+    if secondaries is not None:
+        out.secondaries = secondaries
+    if absorb_next is not None:
+        out.absorb_next = absorb_next
+    if gen_moment is not None:
+        out.gen_moment = gen_moment
+    return out
+
+
 def with_root_offsets(instances: List[Instance]) -> List[Instance]:
     off = 0
     out = []
