@@ -35,13 +35,22 @@ struct Sub {
   static constexpr int value = V;
 };
 
+// v cos(theta) of the current moment in 2^-32 nm/fs fixed point, rounded half to even:
+// adding 1.5*2^52 (|v mu 2^32| < 2^51) leaves the integer in the low mantissa bits,
+// identical to rint()
+__device__ __forceinline__ long long cur_fixed(double v, double mu) {
+  const double vm = v * mu;
+  const double sh = vm * 4294967296.0 + 0x1.8p52;
+  return __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+}
+
 // Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
 // sub-step (density per (z, E, spin), current per (z, spin)), or density to the global
-// bins when its slice does not fit in LDS.
+// bins when its slice does not fit in LDS.  `val` is cur_fixed(v, cos(theta)).
 template <int MODE, int J>
-__device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
-                                        const uint32_t* s_edges, double z, double mu, uint32_t E,
-                                        uint32_t fl, double v) {
+__device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, unsigned char* dyn,
+                                          const uint32_t* s_edges, double z, uint32_t E,
+                                          uint32_t fl, long long val) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
@@ -64,14 +73,15 @@ __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, uns
       }
     }
   }
-  if (a.sub_cur_on[J]) {
-    const double vm = v * mu;
-    // round-half-even to an integer by adding 1.5*2^52 (|vm*2^32| < 2^51): the low
-    // mantissa bits then hold the integer, identical to rint()
-    const double sh = vm * 4294967296.0 + 0x1.8p52;
-    const long long val = __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+  if (a.sub_cur_on[J])
     atomicAdd((unsigned long long*)(dyn + a.lds_cur_at[J]) + zb * 2 + s, (unsigned long long)val);
-  }
+}
+
+template <int MODE, int J>
+__device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
+                                        const uint32_t* s_edges, double z, double mu, uint32_t E,
+                                        uint32_t fl, double v) {
+  deposit_v<MODE, J>(a, I, dyn, s_edges, z, E, fl, cur_fixed(v, mu));
 }
 
 // Merge sub-step J's LDS histogram slices of the workgroup's instance into the int64 bins
@@ -297,7 +307,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
         const double x = a.dt * (Ek * c.itau + I.lay[l].z);
         const double ze = zm + (c.v * mu) * a.h;
-        left = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        // the start lies in the layer and both half steps move the same way
+        left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
         if (!left) {
           const double zs = to_store<F>(ze);
           deposit<MODE, J>(a, I, dyn, s_edges, zs, mu, E, fl, c.v);
@@ -673,6 +684,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           const double E_ev = (double)rE * 0x1p-30;
           const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
           const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+          // u01(w) < x  <=>  w + 0.5 < x 2^32  <=>  w < x 2^32 - 0.5 (both sides exact)
+          const double thr = x * 0x1p32 - 0.5;
+          const long long cv = cur_fixed(c.v, mu);
 #pragma unroll
           for (int j = 0; j < T; ++j) {
             if (left_at < 0) {
@@ -680,13 +694,15 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
               const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step0 + j,
                                        kTagScat, a.key0, a.key1);
               const double ze = zm + vmh;
-              if (zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo) {
+              // z lies in [zlo, zhi] and both half steps move it the same way, so the
+              // step stays in the layer iff its end does
+              if ((double)w.x < thr || ze > c.zhi || ze < c.zlo) {
                 left_at = j;
               } else {
                 z = to_store<F>(ze);
-                if (j == 0) deposit<MODE, 0>(a, I, dyn, s_edges, z, mu, rE, rfl, c.v);
+                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, s_edges, z, rE, rfl, cv);
                 if constexpr (T > 1)
-                  if (j == 1) deposit<MODE, T - 1>(a, I, dyn, s_edges, z, mu, rE, rfl, c.v);
+                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, s_edges, z, rE, rfl, cv);
                 lc[j].dep += 1;
                 n_fast[j] += 1;
               }
