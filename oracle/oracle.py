@@ -48,6 +48,8 @@ class _Instance(C.Structure):
         ("src_e_lo", C.c_uint32 * 2), ("src_e_span", C.c_uint32 * 2),
         ("sched", C.POINTER(C.c_int64)), ("root_offset", C.c_uint64),
         ("nz", C.c_int32), ("inv_dz", C.c_double),
+        ("e_nodes", C.c_int32), ("e_scale", C.c_double),
+        ("v_node", C.POINTER(C.c_double)), ("r_node", C.POINTER(C.c_double)),
     ]
 
 
@@ -170,6 +172,11 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
         s.root_offset = it.root_offset
         s.nz = it.nz
         s.inv_dz = it.inv_dz
+        if getattr(it, "v_tab", None) is not None:
+            s.e_nodes = int(it.v_tab.shape[1])
+            s.e_scale = float(it.e_scale)
+            s.v_node = _ptr(arr(it.v_tab, np.float64), C.c_double)
+            s.r_node = _ptr(arr(it.r_tab, np.float64), C.c_double)
     P = _Problem()
     P.n_instances = len(problem.instances)
     P.inst = insts

@@ -157,8 +157,28 @@ static double transmission(const orc_instance* I, int t, uint32_t E, int* k0, do
   return tab[k] + (tab[k + 1] - tab[k]) * f;
 }
 
-static double speed(const orc_instance* I, int layer, int spin) {
-  return I->v[I->ch_of[layer * 2 + spin]];
+/* Linear interpolation on n equidistant nodes at E = k / scale eV, clamped beyond the last
+ * (the same rule as the transmission tables). */
+static double node_interp(const double* tab, int n, double scale, uint32_t E) {
+  const double x = ((double)E * 0x1p-30) * scale;
+  const int k = (int)floor(x);
+  if (k >= n - 1) return tab[n - 1];
+  const double f = x - (double)k;
+  return tab[k] + (tab[k + 1] - tab[k]) * f;
+}
+
+/* Speed of the carrier's channel in `layer` at energy E (Fig. 1(a)). */
+static double speed(const orc_instance* I, int layer, int spin, uint32_t E) {
+  const int c = I->ch_of[layer * 2 + spin];
+  if (I->e_nodes > 0) return node_interp(I->v_node + (int64_t)c * I->e_nodes, I->e_nodes, I->e_scale, E);
+  return I->v[c];
+}
+
+/* Energy dependence of the inelastic rate, 1/tau(E) = inv_tau0 * Ek (Fig. 1(b), Eq. 2). */
+static double rate_shape(const orc_problem* P, const orc_instance* I, int c, uint32_t E) {
+  if (I->e_nodes > 0) return node_interp(I->r_node + (int64_t)c * I->e_nodes, I->e_nodes, I->e_scale, E);
+  const double E_ev = (double)E * 0x1p-30;
+  return P->tau_exp == 2 ? E_ev * E_ev : 1.0;
 }
 
 /* Transport over half a step, Eq. (18): straight flight at v cos(theta); full reflection
@@ -171,7 +191,7 @@ static void half_step(worker* W, particle* p, int n, uint32_t tag) {
   const double h = 0.5 * P->dt;
   const int L = I->n_layers;
   uint32_t uid_lo = p->root, uid_hi = p->lin;
-  double z_end = p->z + (speed(I, p->layer, p->spin) * p->mu) * h;
+  double z_end = p->z + (speed(I, p->layer, p->spin, p->E) * p->mu) * h;
   int draws = 0, hits = 0;
   for (;;) {
     const int l = p->layer;
@@ -201,7 +221,7 @@ static void half_step(worker* W, particle* p, int n, uint32_t tag) {
     draws++;
     const int base = I->n_channels + t * I->t_entries + k0;
     if (unif(w[0]) < T) {
-      const double r = speed(I, nl, p->spin) / speed(I, l, p->spin);
+      const double r = speed(I, nl, p->spin, p->E) / speed(I, l, p->spin, p->E);
       z_end = b + (z_end - b) * r;
       p->layer = nl;
       p->ev[1]++;
@@ -228,9 +248,9 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
   const int l = p->layer, c = I->ch_of[l * 2 + p->spin];
   uint32_t w[4];
   draw(P, p->root, p->lin, (uint32_t)n, TAG_SCAT, w);
-  /* Eq. (2): 1/tau_eff = 1/tau_el + 1/tau(E); tau(E) = tau0 (1 eV / E)^tau_exp */
-  const double E_ev = (double)p->E * 0x1p-30;
-  const double Ek = P->tau_exp == 2 ? E_ev * E_ev : 1.0;
+  /* Eq. (2): 1/tau_eff = 1/tau_el + 1/tau(E); 1/tau(E) = inv_tau0 * Ek with Ek = (E/1 eV)^
+   * tau_exp, or the channel's rate table */
+  const double Ek = rate_shape(P, I, c, p->E);
   const double rate = Ek * I->inv_tau0[c] + I->inv_tau_el[l];
   const double x = P->dt * rate;
   const double prob = -expm1(-x);
@@ -333,7 +353,7 @@ static void deposit(worker* W, particle* p, int n) {
     }
   }
   if (n % P->cur_stride == 0) {
-    const double vm = speed(I, p->layer, p->spin) * p->mu;
+    const double vm = speed(I, p->layer, p->spin, p->E) * p->mu;
     const int64_t val = llrint(vm * 4294967296.0);
     const int64_t idx = W->cur_off + ((int64_t)(n / P->cur_stride) * I->nz + zb) * 2 + p->spin;
 #pragma omp atomic

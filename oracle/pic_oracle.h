@@ -38,6 +38,14 @@ typedef struct {
   uint64_t root_offset;
   int32_t nz;
   double inv_dz;
+  /* optional energy-dependent channels (Fig. 1: v(E), tau(E)): with e_nodes > 0 the speed
+   * of channel c is the linear interpolation of v_node[c][.] and 1/tau_in is inv_tau0[c]
+   * times the interpolation of r_node[c][.] (tau_exp is then ignored); nodes at
+   * E = k / e_scale eV, k < e_nodes, clamped beyond the last */
+  int32_t e_nodes;
+  double e_scale;
+  const double* v_node;       /* [C][e_nodes] nm/fs */
+  const double* r_node;       /* [C][e_nodes] relative inelastic rate */
 } orc_instance;
 
 typedef struct {

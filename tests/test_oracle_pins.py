@@ -152,6 +152,58 @@ def test_ballistic_bilayer_transparent_event_driven(oracle_lib):
         assert l == r2["layer"][b]
 
 
+def _tabled(inst, v_tab, r_tab, scale):
+    inst = replace(inst)
+    inst.v_tab, inst.r_tab, inst.e_scale = v_tab, r_tab, scale
+    return inst
+
+
+def test_energy_tables_flight_interpolation_and_rate(oracle_lib):
+    """Energy-dependent channels (Fig. 1 inputs).  (1) A table linear in E gives the
+    linear speed at any energy: the half-step transport through a transparent Fe/Au
+    interface equals an exact flight by hit times at v = a_c + b_c E.  (2) At a node energy
+    the inelastic probability is 1 - exp(-dt inv_tau0 r_k): the primaries without an event
+    after n steps are binomial with (1-p)^n."""
+    nodes, scale = 64, 32.0                # nodes at k / 32 eV
+    e = np.arange(nodes) / scale
+    a = np.array([0.55, 0.25, 0.9, 0.9])
+    b = np.array([0.05, 0.1, 0.2, 0.2])
+    v_tab = a[:, None] + b[:, None] * e[None, :]
+    r_tab = np.tile(1.0 + 0.5 * e, (4, 1))
+    E0 = 1.2345                            # between nodes
+
+    def prob(n):
+        inst = W.make_instance(W.bilayer(15.0, 40.0), n_primaries=1200, n_steps=n,
+                               transparent=True, tau0=(INF, INF, INF, INF), e0_ev=(E0, E0))
+        return W.Problem([_tabled(inst, v_tab, r_tab, scale)], seed=5, dt=1.0, n_steps=n,
+                         state_fp64=True)
+
+    r1 = _run(oracle_lib, prob(2), records=True).records
+    r2 = _run(oracle_lib, prob(80), records=True).records
+    inst = replace(prob(2).instances[0])
+    Efx = r1["E"][0]
+    assert np.all(r1["E"] == Efx)
+    inst.v = a + b * (float(Efx) * 2.0 ** -30)
+    o1, o2 = np.argsort(r1["uid"]), np.argsort(r2["uid"])
+    for i, j in zip(o1, o2):
+        z, mu, l = _event_driven_flight(r1["z"][i], r1["mu"][i], r1["layer"][i],
+                                        r1["spin"][i], 78.0, inst)
+        assert abs(z - r2["z"][j]) < 1e-8
+        assert mu == r2["mu"][j] and l == r2["layer"][j]
+    # (2) first-event survival at a node energy
+    k, n, dt, tau0, N = 40, 30, 1.0, 20.0, 20000
+    hom = W.homogeneous(thickness=1e4, n_primaries=N, n_steps=n, tau0=tau0, tau_exp=0,
+                        dt=dt, e0_ev=k / scale, secondaries=False, e_min_ev=0.0,
+                        src=(5000.0, 5000.0))
+    hom.instances[0] = _tabled(hom.instances[0], v_tab, r_tab, scale)
+    rec = _run(oracle_lib, hom, records=True).records
+    p = -math.expm1(-dt * (1.0 / tau0) * r_tab[2, k])
+    q = (1 - p) ** n
+    frac = np.mean(rec["ev"][:, 0] == 0)
+    se = math.sqrt(q * (1 - q) / N)
+    assert abs(frac - q) < 4 * se, (frac, q, se)
+
+
 def test_interface_transmission_fraction(oracle_lib):
     """Each interface hit is an independent Bernoulli(T) draw (Sec. III.A)."""
     T = 0.3

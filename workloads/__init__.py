@@ -93,6 +93,16 @@ class Instance:
     nz: int                  # depth bins
     inv_dz: float            # 1 / depth-bin width (1/nm)
     layers: List[Layer] = field(default_factory=list)
+    # optional energy-dependent channels: speed v_tab[c, k] and relative inelastic rate
+    # r_tab[c, k] (1/tau = inv_tau0[c] * r) at E = k / e_scale eV; None = constant speed
+    # and tau = tau0 (1 eV/E)^tau_exp
+    v_tab: Optional[np.ndarray] = None
+    r_tab: Optional[np.ndarray] = None
+    e_scale: float = 0.0
+
+    @property
+    def e_nodes(self) -> int:
+        return 0 if self.v_tab is None else int(self.v_tab.shape[1])
 
     @property
     def n_layers(self) -> int:
@@ -299,12 +309,24 @@ def spin_valve(fe1: float = 15.0, au: float = 100.0, fe2: float = 15.0, parallel
     return [Layer("Fe", fe1, +1), Layer("Au", au, 0), Layer("Fe", fe2, +1 if parallel else -1)]
 
 
+def synthetic_channel_tables(v: Sequence[float], nodes: int = 64, e_max: float = 2.0):
+    """Smooth synthetic energy dependences standing in for Fig. 1 (the ab-initio curves are
+    not available): speeds rising as sqrt(1 + E / 1 eV) from the channel's speed at
+    E = 0, and relative inelastic rates (E/1 eV)^2 + 0.05 (Fermi-liquid-like, finite at
+    E_F).  Returns (v_tab (C, nodes), r_tab (C, nodes), e_scale)."""
+    e = np.arange(nodes) * (e_max / (nodes - 1))
+    v_tab = np.stack([vc * np.sqrt(1.0 + e) for vc in v]).astype(np.float64)
+    r_tab = np.stack([e * e + 0.05 for _ in v]).astype(np.float64)
+    return v_tab, r_tab, (nodes - 1) / e_max
+
+
 def variant(problem: Problem, *, tau_el: Optional[float] = None, transparent: bool = False,
             secondaries: Optional[bool] = None, absorb_next: Optional[bool] = None,
-            gen_moment: Optional[bool] = None) -> Problem:
+            gen_moment: Optional[bool] = None, energy_tables: bool = False) -> Problem:
     """A copy of `problem` with the physics switches of the paper's comparisons (Sec. V):
     an elastic channel of lifetime tau_el in every layer, transparent interfaces (T = 1),
-    secondaries on / off, removal at the next event, and the generation moment."""
+    secondaries on / off, removal at the next event, the generation moment, and
+    energy-dependent speeds and lifetimes (synthetic tables)."""
     insts = []
     for it in problem.instances:
         it = replace(it)
@@ -312,6 +334,8 @@ def variant(problem: Problem, *, tau_el: Optional[float] = None, transparent: bo
             it.inv_tau_el = np.full(it.n_layers, 1.0 / tau_el if tau_el > 0 else 0.0)
         if transparent:
             it.T = np.ones_like(it.T)
+        if energy_tables:
+            it.v_tab, it.r_tab, it.e_scale = synthetic_channel_tables(it.v)
         insts.append(it)
     out = replace(problem, instances=insts)
     if secondaries is not None:
