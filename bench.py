@@ -203,6 +203,7 @@ def variants_leg(prob, tuning: dict):
         "elastic_30fs": dict(tau_el=30.0),
         "transparent_interfaces": dict(transparent=True),
         "no_secondaries": dict(secondaries=False),
+        "energy_dependent_channels": dict(energy_tables=True),
     }
     for name, kw in cases.items():
         sim = PicSim(W.variant(prob, **kw), device="cuda:0")

@@ -108,6 +108,16 @@ typedef struct {
   uint64_t root_offset;                     /* global id of its first primary */
   int32_t  nz;                              /* depth bins [k/inv_dz, (k+1)/inv_dz) */
   double   inv_dz;
+  /* Optional energy-dependent channels (Fig. 1: v(E) and tau(E) per material and spin).
+   * e_nodes = 0: speed v[c] and 1/tau_in = inv_tau0[c] (E/1 eV)^tau_exp.  e_nodes in
+   * 2..PIC_MAX_TENTRIES: nodes at E = k / e_scale eV (k < e_nodes); the speed of channel c
+   * is the linear interpolation of v_node[c][.] (> 0) and 1/tau_in = inv_tau0[c] times the
+   * interpolation of r_node[c][.] (>= 0, tau_exp ignored), both clamped to the last node
+   * above it (the rule of the transmission tables).  v[] is then unused. */
+  int32_t  e_nodes;
+  double   e_scale;                         /* 1/eV, > 0 when e_nodes > 0 */
+  double   v_node[PIC_MAX_CHANNELS][PIC_MAX_TENTRIES];
+  double   r_node[PIC_MAX_CHANNELS][PIC_MAX_TENTRIES];
 } pic_instance;
 
 typedef struct {

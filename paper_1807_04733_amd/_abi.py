@@ -51,6 +51,9 @@ class PicInstance(C.Structure):
         ("src_e_lo", C.c_uint32 * 2), ("src_e_span", C.c_uint32 * 2),
         ("n_primaries", C.c_int64), ("root_offset", C.c_uint64),
         ("nz", C.c_int32), ("inv_dz", C.c_double),
+        ("e_nodes", C.c_int32), ("e_scale", C.c_double),
+        ("v_node", (C.c_double * MAX_TENTRIES) * MAX_CHANNELS),
+        ("r_node", (C.c_double * MAX_TENTRIES) * MAX_CHANNELS),
     ]
 
 

@@ -73,12 +73,10 @@ struct AdjOps {
   }
 };
 
-__device__ __forceinline__ double x_inelastic(const StepArgs& a, const DevInst& I, uint32_t fl,
-                                              uint32_t E) {
+__device__ __forceinline__ double x_inelastic(const StepArgs& a, const DevInst& I, const double* et,
+                                              uint32_t fl, uint32_t E) {
   const int l = layer_of(fl), s = (int)(fl & kSpinMask);
-  const double E_ev = (double)E * 0x1p-30;
-  const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-  return a.dt * (Ek * I.chan[l][s].y);
+  return a.dt * inel_rate_at(I, et, a.tau_exp2 != 0, l, s, E);
 }
 
 // Interface decisions of a half step become score terms on the table nodes.
@@ -87,6 +85,7 @@ struct HitScore {
   const AdjOps<ADJ>& ops;
   const StepArgs& a;
   const DevInst& I;
+  const double* et;
   AdjLane& L;
   uint32_t& fl;
   uint32_t E;
@@ -95,7 +94,7 @@ struct HitScore {
     if (ADJ == 2) return;
     const int s = (int)(fl & kSpinMask);
     const uint32_t flx = (fl & ~(kLayerMask << kLayerShift)) | ((uint32_t)layer << kLayerShift);
-    ops.flush(L, fl, upto, I.chi[layer][s], x_inelastic(a, I, flx, E));
+    ops.flush(L, fl, upto, I.chi[layer][s], x_inelastic(a, I, et, flx, E));
     const int TE = I.t_entries;
     int k0 = 0;
     double w0 = 1.0, w1 = 0.0;
@@ -123,9 +122,10 @@ struct HitScore {
 
 // Deposit weight of a carrier at the end of step n: g of its density bin (weight 1) plus
 // g of its current bin times v*cos(theta) (the fixed-point value the forward deposits).
-__device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst& I, double z,
-                                                 double mu, uint32_t E, uint32_t fl,
-                                                 const uint32_t* s_edges, const double* s_gcur) {
+__device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst& I,
+                                                 const double* et, double z, double mu, uint32_t E,
+                                                 uint32_t fl, const uint32_t* s_edges,
+                                                 const double* s_gcur) {
   const StepArgs& a = A.s;
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
@@ -138,7 +138,7 @@ __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst
   if (a.cur_on && A.g_cur) {
     const double gc = s_gcur[zb * 2 + s];
     if (gc != 0.0) {
-      const double vm = I.chan[layer_of(fl)][s].x * mu;
+      const double vm = speed_at(I, et, layer_of(fl), s, E) * mu;
       const double sh = vm * 4294967296.0 + 0x1.8p52;
       const long long val = __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
       g += gc * ((double)val * 0x1p-32);
@@ -149,12 +149,12 @@ __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst
 
 template <int ADJ>
 __device__ __forceinline__ void on_deposit(const AdjOps<ADJ>& ops, const StepArgs& a,
-                                           const DevInst& I, AdjLane& L, uint32_t& fl, uint32_t E,
-                                           double g, uint32_t step) {
+                                           const DevInst& I, const double* et, AdjLane& L,
+                                           uint32_t& fl, uint32_t E, double g, uint32_t step) {
   if (g == 0.0) return;
   const AdjArgs& A = ops.A;
   if (ADJ == 1) {
-    ops.flush(L, fl, step + 1, I.chi[layer_of(fl)][fl & kSpinMask], x_inelastic(a, I, fl, E));
+    ops.flush(L, fl, step + 1, I.chi[layer_of(fl)][fl & kSpinMask], x_inelastic(a, I, et, fl, E));
     for (int k = 0; k < A.K; ++k) atomicAdd(&ops.s_grad[k], g * A.S[L.row * A.K + k]);
   }
   if (ADJ == 2) A.r[L.row] += g;
@@ -175,11 +175,14 @@ __device__ __forceinline__ int append_slot(bool want, int* s_app, int tail0) {
 template <typename F, int ADJ>
 __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
   const StepArgs& a = A.s;
-  // dynamic LDS: this step's slice of dL/d(current) for the workgroup's instance, then
-  // one general-path slot queue per wave
+  // dynamic LDS: this step's slice of dL/d(current) for the workgroup's instance, one
+  // general-path slot queue per wave, then the instance's energy tables (if any)
   extern __shared__ double s_gcur[];
   uint32_t* s_slow =
       (uint32_t*)((unsigned char*)s_gcur + (((size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15));
+  double* const s_etab = (double*)((unsigned char*)s_slow + (blockDim.x / 64) * kSlowQueueBytes);
+  const double* const et = a.etab ? s_etab : nullptr;
+  const bool tau2 = a.tau_exp2 != 0;
   __shared__ DevInst s_inst;
   __shared__ double s_grad[kMaxK];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
@@ -213,6 +216,12 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         const double* gsl = A.g_cur + Ig.cur_off + (int64_t)a.cur_slot * Ig.nz * 2;
         for (int i = tid; i < Ig.nz * 2; i += blockDim.x) s_gcur[i] = gsl[i];
       }
+      if (a.etab) {
+        const DevInst& G = a.inst[inst];
+        const int n = 2 * (int)G.n_ch * G.e_nodes;
+        const double* tsrc = a.etab + G.etab_off;
+        for (int i = tid; i < n; i += blockDim.x) s_etab[i] = tsrc[i];
+      }
       cur_inst = inst;
     }
     if (tid == 0) {
@@ -245,18 +254,18 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       if (alive0) {
         HitCounts hc{0, 0, 0};
         {
-          const HitScore<ADJ> hs{ops, a, I, L, fl, E, step};
-          half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad, hs);
+          const HitScore<ADJ> hs{ops, a, I, et, L, fl, E, step};
+          half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad, et,
+                    hs);
         }
         const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
         const int l = layer_of(fl);
         const int s = (int)(fl & kSpinMask);
-        const double E_ev = (double)E * 0x1p-30;
-        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
         const double itel = I.lay[l].z;
-        const double rate = Ek * I.chan[l][s].y + itel;
+        const double inel = inel_rate_at(I, et, tau2, l, s, E);
+        const double rate = inel + itel;
         const double x = a.dt * rate;
-        const double x_in = a.dt * (Ek * I.chan[l][s].y);
+        const double x_in = a.dt * inel;
         const double u0 = u01(w.x);
         bool event;
         if (u0 >= x) event = false;
@@ -304,13 +313,13 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
                 AdjLane CL{cg, lo, L.R, L.haveR};
                 HitCounts chc{0, 0, 0};
                 {
-                  const HitScore<ADJ> hs{ops, a, I, CL, cfl, E2, step + 1};
+                  const HitScore<ADJ> hs{ops, a, I, et, CL, cfl, E2, step + 1};
                   half_push(I, cz, cmu, cfl, E2, lo, lin, step, kTagHalf2, a.h, a.key0, a.key1,
-                            chc, bad, hs);
+                            chc, bad, et, hs);
                 }
                 cz = to_store<F>(cz);
-                const double g = deposit_weight(A, I, cz, cmu, E2, cfl, s_edges, s_gcur);
-                on_deposit<ADJ>(ops, a, I, CL, cfl, E2, g, step);
+                const double g = deposit_weight(A, I, et, cz, cmu, E2, cfl, s_edges, s_gcur);
+                on_deposit<ADJ>(ops, a, I, et, CL, cfl, E2, g, step);
                 gz[cg] = (F)cz;
                 gmu[cg] = (F)cmu;
                 a.E[cg] = E2;
@@ -325,12 +334,13 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         }
         if (!died) {
           {
-            const HitScore<ADJ> hs{ops, a, I, L, fl, E, step + 1};
-            half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad, hs);
+            const HitScore<ADJ> hs{ops, a, I, et, L, fl, E, step + 1};
+            half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad, et,
+                      hs);
           }
           z = to_store<F>(z);
-          const double g = deposit_weight(A, I, z, mu, E, fl, s_edges, s_gcur);
-          on_deposit<ADJ>(ops, a, I, L, fl, E, g, step);
+          const double g = deposit_weight(A, I, et, z, mu, E, fl, s_edges, s_gcur);
+          on_deposit<ADJ>(ops, a, I, et, L, fl, E, g, step);
         } else {
           z = to_store<F>(z);
           fl |= kDead;
@@ -382,8 +392,8 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         hi = (uint32_t)(u >> 32);
         const int d = a.z_phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
-          const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
-          z = replay_flights<F>(z, (c.v * mu) * a.h, d);
+          const double v = speed_at(I, et, layer_of(fl), (int)(fl & kSpinMask), E);
+          z = replay_flights<F>(z, (v * mu) * a.h, d);
         }
       }
       general(false, g, z, mu, E, fl, lo, hi);
@@ -423,23 +433,21 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       bool slow = false;
       if (from_soa && !(rfl & kDead)) {
         const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
-        const LayCache c = load_lay(I, l, s);
+        const LayCache c = load_lay<true>(I, et, tau2, l, s, rE);
         const double mu = (double)rmu;
         const uint32_t st = (rfl >> kStampShift) & kStampMask;
         const double z0 = replay_flights<F>((double)rz, (c.v * mu) * a.h, a.z_phase - (int)st);
         const double zm = z0 + (c.v * mu) * a.h;
         const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
                                  a.key1);
-        const double E_ev = (double)rE * 0x1p-30;
-        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+        const double x = a.dt * (c.itau + I.lay[l].z);
         const double ze = zm + (c.v * mu) * a.h;
         slow = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
         if (!slow) {
           const double zs = to_store<F>(ze);
           const int64_t gi = base + t;
           if (ADJ != 3) {
-            const double g = deposit_weight(A, I, zs, mu, rE, rfl, s_edges, s_gcur);
+            const double g = deposit_weight(A, I, et, zs, mu, rE, rfl, s_edges, s_gcur);
             if (ADJ == 1 && g != 0.0) slow = true;
             if (ADJ == 2 && g != 0.0) A.r[gi] += g;
           }
@@ -539,7 +547,9 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs A, uint32_t n_steps) 
     if (ADJ == 3) {
       AdjLane L{gi, lo, 0.0, false};
       const uint32_t E = a.E[gi];
-      ops.flush(L, fl, n_steps, I.chi[layer_of(fl)][fl & kSpinMask], x_inelastic(a, I, fl, E));
+      // energy tables read from global memory in this one-off pass
+      const double* et = a.etab ? a.etab + I.etab_off : nullptr;
+      ops.flush(L, fl, n_steps, I.chi[layer_of(fl)][fl & kSpinMask], x_inelastic(a, I, et, fl, E));
     }
   }
   __syncthreads();
@@ -551,7 +561,8 @@ __global__ void __launch_bounds__(256) k_adj_final(AdjArgs A, uint32_t n_steps) 
 template <typename F>
 static hipError_t launch_adj_prec(const AdjArgs& A, int adj, int grid, int block, hipStream_t s) {
   const size_t lds = (((size_t)A.s.lds_cur_words * 8 + 15) & ~(size_t)15) +
-                     (size_t)(block / 64) * kSlowQueueBytes;
+                     (size_t)(block / 64) * kSlowQueueBytes +
+                     (A.s.etab ? (size_t)A.s.etab_words * 8 : 0);
   switch (adj) {
     case 1: hipLaunchKernelGGL((k_adj<F, 1>), dim3(grid), dim3(block), lds, s, A); break;
     case 2: hipLaunchKernelGGL((k_adj<F, 2>), dim3(grid), dim3(block), lds, s, A); break;

@@ -42,15 +42,17 @@ struct Plan {
   std::vector<int32_t> slab_inst, slab_k, slab_cap;
   std::vector<int64_t> slab_base;
   std::vector<int32_t> n_slabs_of, slab0_of;
-  std::vector<int64_t> dens_off, cur_off, gen_off;
+  std::vector<int64_t> dens_off, cur_off, gen_off, etab_off;
   int64_t capacity = 0, dens_len = 0, cur_len = 0, gen_len = 0;
+  int64_t etab_len = 0;        // doubles of all energy tables
+  int etab_max = 0;            // doubles of the largest instance's tables
   int n_dslots = 0, n_cslots = 0, state_bytes = 4;
   bool debug = false;
   // byte offsets inside the workspace
   int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
   int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
   int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
-  int64_t off_stats, off_gen = -1;
+  int64_t off_stats, off_gen = -1, off_etab = -1;
   int64_t off_grad = -1, off_S = -1, off_r = -1, off_R = -1;
   int K = 0;
   int64_t n_roots = 0;
@@ -91,15 +93,27 @@ pic_status validate(const pic_config* c) {
       for (int d = 0; d < 2; ++d)
         for (int s = 0; s < 2; ++s)
           if (I.tt_of[k][d][s] < 0 || I.tt_of[k][d][s] >= I.n_ttables) return fail(PIC_EINVAL, w + "bad tt_of");
+    if (I.e_nodes != 0 && (I.e_nodes < 2 || I.e_nodes > PIC_MAX_TENTRIES))
+      return fail(PIC_EINVAL, w + "e_nodes must be 0 or 2..PIC_MAX_TENTRIES");
+    // energies are below 4 eV: the node index (E e_scale) must fit an int
+    if (I.e_nodes && (!(I.e_scale > 0.0) || !(I.e_scale <= 1e8)))
+      return fail(PIC_EINVAL, w + "e_scale must be in (0, 1e8]");
     for (int ch = 0; ch < I.n_channels; ++ch) {
-      if (!(I.v[ch] > 0.0) || !std::isfinite(I.v[ch])) return fail(PIC_EINVAL, w + "speeds must be > 0");
+      if (!I.e_nodes && (!(I.v[ch] > 0.0) || !std::isfinite(I.v[ch])))
+        return fail(PIC_EINVAL, w + "speeds must be > 0");
       if (!(I.inv_tau0[ch] >= 0.0) || !std::isfinite(I.inv_tau0[ch])) return fail(PIC_EINVAL, w + "inv_tau0 must be >= 0");
+      for (int k = 0; k < I.e_nodes; ++k) {
+        if (!(I.v_node[ch][k] > 0.0) || !std::isfinite(I.v_node[ch][k]))
+          return fail(PIC_EINVAL, w + "tabled speeds must be > 0");
+        if (!(I.r_node[ch][k] >= 0.0) || !std::isfinite(I.r_node[ch][k]))
+          return fail(PIC_EINVAL, w + "tabled rates must be >= 0");
+      }
     }
     for (int t = 0; t < I.n_ttables; ++t)
       for (int e = 0; e < I.t_entries; ++e)
         if (!(I.T[t][e] >= 0.0 && I.T[t][e] <= 1.0)) return fail(PIC_EINVAL, w + "T outside [0,1]");
-    if (I.t_entries > 1 && (!(I.T_scale > 0.0) || !std::isfinite(I.T_scale)))
-      return fail(PIC_EINVAL, w + "T_scale must be > 0");
+    if (I.t_entries > 1 && (!(I.T_scale > 0.0) || !(I.T_scale <= 1e8)))
+      return fail(PIC_EINVAL, w + "T_scale must be in (0, 1e8]");
     if (!(I.src_z_lo >= I.z_bound[0] && I.src_z_hi <= I.z_bound[I.n_layers] && I.src_z_lo <= I.src_z_hi))
       return fail(PIC_EINVAL, w + "source region outside the stack");
     if (!(I.src_lambda >= 0.0) || !std::isfinite(I.src_lambda)) return fail(PIC_EINVAL, w + "bad src_lambda");
@@ -168,6 +182,10 @@ Plan make_plan(const pic_config* c) {
     p.dens_off.push_back(p.dens_len);
     p.cur_off.push_back(p.cur_len);
     p.gen_off.push_back(p.gen_len);
+    p.etab_off.push_back(p.etab_len);
+    const int et_words = 2 * I.n_channels * I.e_nodes;
+    p.etab_len += et_words;
+    p.etab_max = std::max(p.etab_max, et_words);
     p.dens_len += (int64_t)p.n_dslots * I.nz * c->n_ebins * 2;
     p.cur_len += (int64_t)p.n_cslots * I.nz * 2;
     if (c->flags & PIC_F_GEN_MOMENT) p.gen_len += (int64_t)p.n_dslots * I.nz * 2;
@@ -201,6 +219,7 @@ Plan make_plan(const pic_config* c) {
   p.off_status = take(64);
   p.off_stats = take((int64_t)c->n_steps * 2 * 8);
   if (c->flags & PIC_F_GEN_MOMENT) p.off_gen = take(p.gen_len * 8);
+  if (p.etab_len > 0) p.off_etab = take(p.etab_len * 8);
   if (c->adjoint) {
     const pic_instance& I0 = c->inst[0];
     p.K = I0.n_channels + I0.n_ttables * I0.t_entries;
@@ -226,6 +245,7 @@ struct pic_ctx {
   hipStream_t stream = nullptr;
   uint8_t* ws = nullptr;
   std::vector<DevInst> h_inst;
+  std::vector<double> h_etab;
   std::vector<int64_t> h_inj;
   std::vector<int64_t> h_counters;
   int step = 0;
@@ -287,6 +307,9 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
     if (a) a->lds_gen_at[j] = g ? (int32_t)off : -1;
     if (g) off = (off + (size_t)c->lds_cur_words * 4 + 15) & ~(size_t)15;
   }
+  // the energy tables of the workgroup's instance
+  if (a) a->lds_etab_at = c->plan.etab_max ? (int32_t)off : -1;
+  off = (off + (size_t)c->plan.etab_max * 8 + 15) & ~(size_t)15;
   if (a) {
     a->lds_q_at = (int32_t)off;
     a->lds_q_bytes = (int32_t)step_queue_bytes(n_sub);
@@ -343,6 +366,9 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.status = c->at<uint32_t>(p.off_status);
   a.stats = c->at<unsigned long long>(p.off_stats);
   a.gen = c->at<uint64_t>(p.off_gen);
+  a.etab = c->at<double>(p.off_etab);
+  a.etab_words = p.etab_max;
+  a.lds_etab_at = -1;
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
   a.n_ebins = c->cfg.n_ebins;
@@ -464,6 +490,7 @@ pic_status upload_tables(pic_ctx* c) {
   const Plan& p = c->plan;
   const pic_config& cfg = c->cfg;
   c->h_inst.assign(cfg.n_instances, DevInst{});
+  c->h_etab.assign((size_t)p.etab_len, 0.0);
   int max_tab = 1;
   for (int i = 0; i < cfg.n_instances; ++i) {
     const pic_instance& I = c->inst[i];
@@ -474,11 +501,21 @@ pic_status upload_tables(pic_ctx* c) {
       for (int s = 0; s < 2; ++s)
         D.chan[l][s] = make_double2(I.v[I.ch_of[l][s]], I.inv_tau0[I.ch_of[l][s]]);
     }
+    // speed ratios of constant speeds (with energy tables the kernels divide v(E) values)
     for (int l = 0; l < I.n_layers; ++l)
       for (int s = 0; s < 2; ++s) {
         const double v = I.v[I.ch_of[l][s]];
-        D.ratio[l][s][0] = l + 1 < I.n_layers ? I.v[I.ch_of[l + 1][s]] / v : 1.0;
-        D.ratio[l][s][1] = l > 0 ? I.v[I.ch_of[l - 1][s]] / v : 1.0;
+        D.ratio[l][s][0] = l + 1 < I.n_layers && !I.e_nodes ? I.v[I.ch_of[l + 1][s]] / v : 1.0;
+        D.ratio[l][s][1] = l > 0 && !I.e_nodes ? I.v[I.ch_of[l - 1][s]] / v : 1.0;
+      }
+    D.e_nodes = I.e_nodes;
+    D.e_scale = I.e_nodes ? I.e_scale : 0.0;
+    D.etab_off = p.etab_off[i];
+    D.n_ch = (uint8_t)I.n_channels;
+    for (int ch = 0; ch < I.n_channels; ++ch)
+      for (int k = 0; k < I.e_nodes; ++k) {
+        c->h_etab[p.etab_off[i] + (int64_t)ch * I.e_nodes + k] = I.v_node[ch][k];
+        c->h_etab[p.etab_off[i] + (int64_t)(I.n_channels + ch) * I.e_nodes + k] = I.r_node[ch][k];
       }
     D.T_scale = I.T_scale;
     D.inv_dz = I.inv_dz;
@@ -522,6 +559,9 @@ pic_status upload_tables(pic_ctx* c) {
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_edges), cfg.e_edges, PIC_MAX_EBINS * 4,
                          hipMemcpyHostToDevice, c->stream));
+  if (p.etab_len > 0)
+    HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_etab), c->h_etab.data(), c->h_etab.size() * 8,
+                           hipMemcpyHostToDevice, c->stream));
   // the copies read pageable host memory; finish them before the host buffers can change
   HIP_TRY(hipStreamSynchronize(c->stream));
   return PIC_OK;

@@ -68,6 +68,38 @@ __device__ __forceinline__ double trans_prob(const DevInst& I, int t, uint32_t E
   return tab[k] + (tab[k + 1] - tab[k]) * f;
 }
 
+// Linear interpolation on n equidistant energy nodes at E = k / scale eV, clamped beyond
+// the last node (the rule of the transmission tables).
+__device__ __forceinline__ double node_interp(const double* tab, int n, double scale, uint32_t E) {
+  const double x = ((double)E * 0x1p-30) * scale;
+  const int k = (int)floor(x);
+  if (k >= n - 1) return tab[n - 1];
+  const double f = x - (double)k;
+  return tab[k] + (tab[k + 1] - tab[k]) * f;
+}
+
+// Speed of the channel of (layer l, spin s) at energy E (Fig. 1(a)); `et` points at the
+// instance's energy tables (used only when it has them).
+__device__ __forceinline__ double speed_at(const DevInst& I, const double* et, int l, int s,
+                                           uint32_t E) {
+  if (I.e_nodes) return node_interp(et + I.chi[l][s] * I.e_nodes, I.e_nodes, I.e_scale, E);
+  return I.chan[l][s].x;
+}
+
+// Inelastic rate 1/tau(E) of (layer l, spin s), Eq. (2) and Fig. 1(b): 1/tau0 times the
+// channel's rate table at E, or times (E / 1 eV)^2 (tau2) or 1.
+__device__ __forceinline__ double inel_rate_at(const DevInst& I, const double* et, bool tau2,
+                                               int l, int s, uint32_t E) {
+  if (I.e_nodes) {
+    const double r =
+        node_interp(et + ((int)I.n_ch + I.chi[l][s]) * I.e_nodes, I.e_nodes, I.e_scale, E);
+    return r * I.chan[l][s].y;
+  }
+  const double E_ev = (double)E * 0x1p-30;
+  const double Ek = tau2 ? E_ev * E_ev : 1.0;
+  return Ek * I.chan[l][s].y;
+}
+
 struct HitCounts {
   uint32_t tr, ri, rs;
 };
@@ -84,10 +116,11 @@ template <class OnHit = NoHitObserver>
 __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& mu, uint32_t& fl,
                                           uint32_t E, uint32_t lo, uint32_t hi, uint32_t step,
                                           uint32_t tag, double h, uint32_t k0, uint32_t k1,
-                                          HitCounts& hc, bool& bad, OnHit on_hit = OnHit()) {
+                                          HitCounts& hc, bool& bad, const double* et,
+                                          OnHit on_hit = OnHit()) {
   int l = layer_of(fl);
   const int s = (int)(fl & kSpinMask);
-  const double v = I.chan[l][s].x;
+  const double v = speed_at(I, et, l, s, E);
   double ze = z + (v * mu) * h;
   double zlo = I.lay[l].x, zhi = I.lay[l].y;
   if (ze > zhi || ze < zlo) {
@@ -124,8 +157,10 @@ __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& m
       ++draws;
       on_hit(tab, l, T, go);
       if (go) {
-        // speed ratio new/old layer, divided once on the host (same IEEE quotient)
-        const double r = I.ratio[l][s][up ? 0 : 1];
+        // speed ratio new/old layer (constant speeds: divided once on the host, the same
+        // IEEE quotient)
+        const double r = I.e_nodes ? speed_at(I, et, nl, s, E) / speed_at(I, et, l, s, E)
+                                   : I.ratio[l][s][up ? 0 : 1];
         ze = b + (ze - b) * r;
         l = nl;
         zlo = I.lay[l].x;
@@ -143,7 +178,9 @@ __device__ __forceinline__ void half_push(const DevInst& I, double& z, double& m
 }
 
 // Table values of a carrier's (layer, spin), kept in registers through the step and
-// reloaded from LDS only when the carrier changes layer.
+// reloaded from LDS only when the carrier changes layer (or energy, with energy tables).
+// ET false: v and itau = 1/tau0 of the channel, the energy factor of the rate applied at
+// each use (inel_rate).  ET true: v(E) and itau = 1/tau(E) at the carrier's energy.
 struct LayCache {
   double zlo, zhi, v, itau;
 };
@@ -151,6 +188,28 @@ struct LayCache {
 __device__ __forceinline__ LayCache load_lay(const DevInst& I, int l, int s) {
   const double2 C = I.chan[l][s];
   return LayCache{I.lay[l].x, I.lay[l].y, C.x, C.y};
+}
+
+template <bool ET>
+__device__ __forceinline__ LayCache load_lay(const DevInst& I, const double* et, bool tau2, int l,
+                                             int s, uint32_t E) {
+  if constexpr (ET)
+    return LayCache{I.lay[l].x, I.lay[l].y, speed_at(I, et, l, s, E),
+                    inel_rate_at(I, et, tau2, l, s, E)};
+  else
+    return load_lay(I, l, s);
+}
+
+// 1/tau(E) of a cached (layer, spin) at energy E (the same product as inel_rate_at).
+template <bool ET>
+__device__ __forceinline__ double inel_rate(const LayCache& c, bool tau2, uint32_t E) {
+  if constexpr (ET) {
+    return c.itau;
+  } else {
+    const double E_ev = (double)E * 0x1p-30;
+    const double Ek = tau2 ? E_ev * E_ev : 1.0;
+    return Ek * c.itau;
+  }
 }
 
 // n straight flights of a whole step each, from a stored position: the common-path step
@@ -166,7 +225,9 @@ __device__ __forceinline__ double replay_flights(double z, double vmh, int n) {
 
 // Transport half step with the layer's table values cached (same arithmetic and draws
 // as half_push).
-__device__ __forceinline__ void half_push_c(const DevInst& I, LayCache& c, double& z, double& mu,
+template <bool ET>
+__device__ __forceinline__ void half_push_c(const DevInst& I, const double* et, bool tau2,
+                                            LayCache& c, double& z, double& mu,
                                             uint32_t& fl, uint32_t E, uint32_t lo, uint32_t hi,
                                             uint32_t step, uint32_t tag, double h, uint32_t k0,
                                             uint32_t k1, HitCounts& hc, bool& bad) {
@@ -205,10 +266,15 @@ __device__ __forceinline__ void half_push_c(const DevInst& I, LayCache& c, doubl
       }
       ++draws;
       if (go) {
-        const double r = I.ratio[l][s][up ? 0 : 1];
-        ze = b + (ze - b) * r;
+        if constexpr (ET) {
+          const LayCache cn = load_lay<true>(I, et, tau2, nl, s, E);
+          ze = b + (ze - b) * (cn.v / c.v);
+          c = cn;
+        } else {
+          ze = b + (ze - b) * I.ratio[l][s][up ? 0 : 1];
+          c = load_lay(I, nl, s);
+        }
         l = nl;
-        c = load_lay(I, l, s);
         ++hc.tr;
       } else {
         ze = b - (ze - b);

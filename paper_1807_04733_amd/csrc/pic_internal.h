@@ -48,20 +48,23 @@ struct alignas(32) DevInst {
   double ratio[kMaxL][2][2];   // per (layer, spin, direction +z/-z): v_next / v_this
   double T_scale, inv_dz;
   double src_lo, src_hi, src_lambda, src_cd, src_up;
-  double pad0;
+  double e_scale;              // energy tables: nodes at E = k / e_scale eV
   uint32_t e_lo[2], e_span[2];
   int32_t n_layers, t_entries, nz, n_slabs;
   uint64_t root_offset;
   int64_t dens_off, cur_off;   // element offsets of this instance in the global bins
   int64_t gen_off;             // ... in the generation-moment bins
-  int32_t slab0, pad1;
+  int64_t etab_off;            // ... in the energy tables ([v rows | rate rows][channel][node])
+  int32_t slab0, e_nodes;      // e_nodes = 0: constant speeds and rates
   uint8_t tt[kMaxL - 1][2][2]; // transmission table per (interface, direction, spin)
   uint8_t chi[kMaxL][2];       // channel index per (layer, spin) (adjoint parameter slot)
-  uint8_t pad2[4];
+  uint8_t n_ch;                // channels (rows of each energy table)
+  uint8_t pad2[3];
   double T[kMaxT];             // [table][entry]; only the first n_ttables*t_entries used
 };
 // bytes of DevInst that precede the transmission tables
 constexpr int kInstHead = (int)offsetof(DevInst, T);
+static_assert(kInstHead % 16 == 0, "the head is copied in 16-byte words");
 
 struct StepArgs {
   void* z;
@@ -116,6 +119,10 @@ struct StepArgs {
   // the density (LDS slice per sub-step at lds_gen_at, u32), or null
   uint64_t* gen;
   int32_t lds_gen_at[kMaxSub];
+  // energy tables of all instances (binary64, at DevInst::etab_off), or null; copied per
+  // instance into dynamic LDS at lds_etab_at (step kernel; etab_words doubles at most)
+  const double* etab;
+  int32_t lds_etab_at, etab_words;
 };
 
 struct AdjArgs {

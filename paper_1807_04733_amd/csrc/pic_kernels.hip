@@ -28,6 +28,7 @@ namespace pic {
 // Compile-time launch modes of the step kernel.
 constexpr int kModeDebug = 1;       // keep per-particle event counts
 constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slice does not fit)
+constexpr int kModeETab = 8;        // energy-dependent speeds and rates (tables in LDS)
 
 // Compile-time sub-step index for the generic lambdas of k_step.
 template <int V>
@@ -188,8 +189,9 @@ constexpr int kSlowQ1 = 256;
 template <typename F, int T, int MODE>
 __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  // dynamic LDS: [histogram slices of the sub-steps | per wave: newborn queue, slot
-  // queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
+  constexpr bool ET = (MODE & kModeETab) != 0;
+  // dynamic LDS: [histogram slices of the sub-steps | energy tables | per wave: newborn
+  // queue, slot queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ DevInst s_inst;
   __shared__ unsigned long long s_cnt[T][kNC];
@@ -219,6 +221,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   uint32_t* const SQ0 = (uint32_t*)(wq + kChildQueueBytes);
   uint32_t* const SQ1 = SQ0 + kSlowQ0;
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
+  const double* const et = ET ? (const double*)(dyn + a.lds_etab_at) : nullptr;
+  const bool tau2 = a.tau_exp2 != 0;
   int cur_inst = -1;
   bool bad = false;
 
@@ -233,6 +237,13 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       const uint4* src = (const uint4*)&a.inst[inst];
       uint4* dst = (uint4*)&s_inst;
       for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
+      if constexpr (ET) {
+        const DevInst& G = a.inst[inst];
+        const int n = 2 * (int)G.n_ch * G.e_nodes;
+        const double* tsrc = a.etab + G.etab_off;
+        double* tdst = (double*)(dyn + a.lds_etab_at);
+        for (int i = tid; i < n; i += blockDim.x) tdst[i] = tsrc[i];
+      }
       cur_inst = inst;
     }
     if (tid == 0) {
@@ -300,12 +311,10 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       bool left = false;
       if (act) {
         const int l = layer_of(fl);
-        const LayCache c = load_lay(I, l, (int)(fl & kSpinMask));
+        const LayCache c = load_lay<ET>(I, et, tau2, l, (int)(fl & kSpinMask), E);
         const double zm = z + (c.v * mu) * a.h;
         const uint4 w = philox10(lo, hi, step0 + J, kTagScat, a.key0, a.key1);
-        const double E_ev = (double)E * 0x1p-30;
-        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-        const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+        const double x = a.dt * (inel_rate<ET>(c, tau2, E) + I.lay[l].z);
         const double ze = zm + (c.v * mu) * a.h;
         // the start lies in the layer and both half steps move the same way
         left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
@@ -345,14 +354,13 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       if (alive0) {
         const double mu_in = mu;
         const uint32_t fl_in = fl;
-        LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
-        half_push_c(I, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad);
+        LayCache c = load_lay<ET>(I, et, tau2, layer_of(fl), (int)(fl & kSpinMask), E);
+        half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0,
+                        a.key1, hc, bad);
         // ---- scattering over the full step, at the mid-step state
         const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
-        const double E_ev = (double)E * 0x1p-30;
-        const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
         const double itel = I.lay[layer_of(fl)].z;
-        const double rate = Ek * c.itau + itel;
+        const double rate = inel_rate<ET>(c, tau2, E) + itel;
         const double x = a.dt * rate;
         const double u0 = u01(w.x);
         // event iff u0 < p = 1 - exp(-x), decided without the transcendental outside a
@@ -405,7 +413,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           }
         }
         if (!died) {
-          half_push_c(I, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0, a.key1, hc, bad);
+          // with energy tables the speed and rate follow the new energy
+          if constexpr (ET)
+            if (dirty & 2u) c = load_lay<ET>(I, et, tau2, layer_of(fl), (int)(fl & kSpinMask), E);
+          half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
+                          a.key1, hc, bad);
           z = to_store<F>(z);
           deposit<MODE, J>(a, I, dyn, s_edges, z, mu, E, fl, c.v);
           lc[J].dep += 1;
@@ -506,9 +518,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         }
         cfl = cs | (pfl & ~kSpinMask) | (z_next << kStampShift);
         HitCounts h{0, 0, 0};
-        LayCache cc = load_lay(I, l, (int)cs);
-        half_push_c(I, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0, a.key1, h,
-                    bad);
+        LayCache cc = load_lay<ET>(I, et, tau2, l, (int)cs, cE);
+        half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0,
+                        a.key1, h, bad);
         cz = to_store<F>(cz);
         deposit<MODE, J>(a, I, dyn, s_edges, cz, cmu, cE, cfl, cc.v);
         lc[J].dep += 1;
@@ -557,8 +569,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         if (DEBUG) evp = at(sp.ev, g);
         const int d = phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
-          const LayCache c = load_lay(I, layer_of(fl), (int)(fl & kSpinMask));
-          z = replay_flights<F>(z, (c.v * mu) * a.h, d);
+          const double v = ET ? speed_at(I, et, layer_of(fl), (int)(fl & kSpinMask), E)
+                              : I.chan[layer_of(fl)][fl & kSpinMask].x;
+          z = replay_flights<F>(z, (v * mu) * a.h, d);
         }
       }
       return act;
@@ -676,14 +689,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         int left_at = -1;
         if (from_soa && !(rfl & kDead)) {
           const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
-          const LayCache c = load_lay(I, l, s);
+          const LayCache c = load_lay<ET>(I, et, tau2, l, s, rE);
           const double mu = (double)rmu;
           const double vmh = (c.v * mu) * a.h;
           const uint32_t st = (rfl >> kStampShift) & kStampMask;
           double z = replay_flights<F>((double)rz, vmh, a.sub_z_phase[0] - (int)st);
-          const double E_ev = (double)rE * 0x1p-30;
-          const double Ek = a.tau_exp2 ? E_ev * E_ev : 1.0;
-          const double x = a.dt * (Ek * c.itau + I.lay[l].z);
+          const double x = a.dt * (inel_rate<ET>(c, tau2, rE) + I.lay[l].z);
           // u01(w) < x  <=>  w + 0.5 < x 2^32  <=>  w < x 2^32 - 0.5 (both sides exact)
           const double thr = x * 0x1p32 - 0.5;
           const long long cv = cur_fixed(c.v, mu);
@@ -856,13 +867,19 @@ static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL((k_step<F, T, MODE>), dim3(L.grid), dim3(L.block), L.lds, s, a);
 }
 
+constexpr int kDG = kModeDebug | kModeDensGlobal;
+
 template <typename F, int T>
 static hipError_t launch_prec(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s) {
   switch (mode) {
     case 0: launch_mode<F, T, 0>(a, L, s); break;
     case kModeDebug: launch_mode<F, T, kModeDebug>(a, L, s); break;
     case kModeDensGlobal: launch_mode<F, T, kModeDensGlobal>(a, L, s); break;
-    case kModeDebug | kModeDensGlobal: launch_mode<F, T, kModeDebug | kModeDensGlobal>(a, L, s); break;
+    case kDG: launch_mode<F, T, kDG>(a, L, s); break;
+    case kModeETab: launch_mode<F, T, kModeETab>(a, L, s); break;
+    case kModeETab | kModeDebug: launch_mode<F, T, kModeETab | kModeDebug>(a, L, s); break;
+    case kModeETab | kModeDensGlobal: launch_mode<F, T, kModeETab | kModeDensGlobal>(a, L, s); break;
+    case kModeETab | kDG: launch_mode<F, T, kModeETab | kDG>(a, L, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -881,7 +898,11 @@ static hipError_t raise_lds(size_t bytes) {
   for (const void* f : {reinterpret_cast<const void*>(&k_step<F, T, 0>),
                         reinterpret_cast<const void*>(&k_step<F, T, kModeDebug>),
                         reinterpret_cast<const void*>(&k_step<F, T, kModeDensGlobal>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeDebug | kModeDensGlobal>)})
+                        reinterpret_cast<const void*>(&k_step<F, T, kDG>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kModeDebug>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kModeDensGlobal>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kDG>)})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
 }
@@ -896,7 +917,8 @@ hipError_t set_step_lds_limit(size_t bytes) {
 
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
-  const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0);
+  const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
+                   (a.etab ? kModeETab : 0);
   if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
   hipError_t e;
   if (a.n_sub == 2)

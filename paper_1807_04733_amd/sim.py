@@ -51,6 +51,16 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
         s.root_offset = int(it.root_offset)
         s.nz = int(it.nz)
         s.inv_dz = float(it.inv_dz)
+        v_tab = getattr(it, "v_tab", None)
+        if v_tab is not None:
+            # energy-dependent channels: speed and relative inelastic rate per node
+            n = int(v_tab.shape[1])
+            s.e_nodes = n
+            s.e_scale = float(it.e_scale)
+            for c in range(it.n_channels):
+                for k in range(n):
+                    s.v_node[c][k] = float(v_tab[c, k])
+                    s.r_node[c][k] = float(it.r_tab[c, k])
     cfg = _abi.PicConfig()
     cfg.n_instances = len(problem.instances)
     cfg.inst = insts

@@ -69,6 +69,12 @@ def _size(abi, prob, **kw):
     return rc, n.value
 
 
+def test_energy_tables_accepted(abi):
+    prob = W.variant(W.config0(n_primaries=100, n_steps=10), energy_tables=True)
+    rc, n = _size(abi, prob)
+    assert rc == 0 and n > 0
+
+
 def test_workspace_size_grows_with_primaries(abi):
     rc1, a = _size(abi, W.config1(n_primaries=10_000, n_steps=100))
     rc2, b = _size(abi, W.config1(n_primaries=100_000, n_steps=100))
@@ -76,7 +82,8 @@ def test_workspace_size_grows_with_primaries(abi):
 
 
 @pytest.mark.parametrize("breaker", ["z_grid", "T_range", "dt", "tau_exp", "edges", "speed",
-                                     "layers", "roots"])
+                                     "layers", "roots", "e_nodes", "e_scale", "v_node",
+                                     "r_node"])
 def test_invalid_configs_rejected(abi, breaker):
     prob = W.config0(n_primaries=100, n_steps=10)
     inst = prob.instances[0]
@@ -102,6 +109,16 @@ def test_invalid_configs_rejected(abi, breaker):
         inst.tt_of = np.zeros((16, 2, 2), np.int32)
     elif breaker == "roots":
         inst.root_offset = 2 ** 32 - 10
+    elif breaker in ("e_nodes", "e_scale", "v_node", "r_node"):
+        inst.v_tab, inst.r_tab, inst.e_scale = W.synthetic_channel_tables(inst.v)
+        if breaker == "e_nodes":
+            inst.v_tab, inst.r_tab = inst.v_tab[:, :1], inst.r_tab[:, :1]
+        elif breaker == "e_scale":
+            inst.e_scale = 0.0
+        elif breaker == "v_node":
+            inst.v_tab[1, 5] = 0.0
+        else:
+            inst.r_tab[0, 3] = -1e-3
     try:
         rc, _ = _size(abi, prob)
     except ValueError:

@@ -176,6 +176,30 @@ def test_removal_at_next_event(torch_gpu, oracle_mod, sub_steps):
     assert ref.counters[:, 5].sum() == 0          # no secondary is dropped at birth
 
 
+@pytest.mark.parametrize("sub_steps", [1, 2])
+def test_energy_dependent_speeds_and_rates(torch_gpu, oracle_mod, sub_steps):
+    """Speeds v(E) and inelastic rates 1/tau(E) interpolated from per-channel tables
+    (Fig. 1): records, bins and counters equal the oracle's, in one- and two-step
+    launches."""
+    prob = W.variant(W.config1(parallel=True, n_primaries=4000, n_steps=160),
+                     energy_tables=True, gen_moment=True)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=900,
+                        tuning={"sub_steps": sub_steps, "z_every": 4})
+    assert_parity(dev, ref, prob)
+    assert ref.counters[:, 6].sum() > 1000        # many interface transmissions
+
+
+def test_energy_tables_mixed_batch(torch_gpu, oracle_mod):
+    """A batch where one instance has constant speeds (E^2 rate law) and the others
+    energy tables, with energy-dependent transmission and the removal rule."""
+    prob = W.variant(W.config4(n_instances=3, primaries_per_instance=1200, n_steps=300),
+                     energy_tables=True, absorb_next=True)
+    prob.instances[1].v_tab = prob.instances[1].r_tab = None
+    prob.e_min_fx = W.e_fx(0.3)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=400, tuning={"sub_steps": 2})
+    assert_parity(dev, ref, prob)
+
+
 def test_capacity_overflow_is_reported(torch_gpu):
     from paper_1807_04733_amd import PicSim, PicError
     prob = W.config0(n_primaries=2000, n_steps=100)
