@@ -211,7 +211,7 @@ Plan make_plan(const pic_config* c) {
   p.off_slab_k = take(NS * 4);
   p.off_inst = take(NI * (int64_t)sizeof(DevInst));
   p.off_inj = take(NI * ((int64_t)c->n_steps + 1) * 8);
-  p.off_edges = take(PIC_MAX_EBINS * 4);
+  p.off_edges = take(PIC_MAX_EBINS * 4 + kEBuckets);  // edges, then the bucket table
   p.off_dens = take(p.dens_len * 8);
   p.off_cur = take(p.cur_len * 8);
   p.off_counters = take((int64_t)c->n_steps * kNC * 8);
@@ -246,6 +246,7 @@ struct pic_ctx {
   uint8_t* ws = nullptr;
   std::vector<DevInst> h_inst;
   std::vector<double> h_etab;
+  std::vector<uint8_t> h_ebkt;
   std::vector<int64_t> h_inj;
   std::vector<int64_t> h_counters;
   int step = 0;
@@ -359,6 +360,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.inst = c->at<DevInst>(p.off_inst);
   a.inj_cum = c->at<int64_t>(p.off_inj);
   a.e_edges = c->at<uint32_t>(p.off_edges);
+  a.e_bucket = c->at<uint8_t>(p.off_edges + PIC_MAX_EBINS * 4);
   a.dens = c->at<uint64_t>(p.off_dens);
   a.cur = c->at<int64_t>(p.off_cur);
   a.counters = c->at<int64_t>(p.off_counters);
@@ -559,6 +561,15 @@ pic_status upload_tables(pic_ctx* c) {
                          hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_edges), cfg.e_edges, PIC_MAX_EBINS * 4,
                          hipMemcpyHostToDevice, c->stream));
+  // energy-bin bucket table: the bin of the lower end of each bucket of 2^22 units
+  c->h_ebkt.assign(kEBuckets, 0);
+  for (int b = 0, k = 0; b < kEBuckets; ++b) {
+    const uint64_t lo = (uint64_t)b << kEBucketShift;
+    while (k + 1 < cfg.n_ebins && cfg.e_edges[k + 1] <= lo) ++k;
+    c->h_ebkt[b] = (uint8_t)k;
+  }
+  HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_edges + PIC_MAX_EBINS * 4), c->h_ebkt.data(),
+                         kEBuckets, hipMemcpyHostToDevice, c->stream));
   if (p.etab_len > 0)
     HIP_TRY(hipMemcpyAsync(c->at<void>(p.off_etab), c->h_etab.data(), c->h_etab.size() * 8,
                            hipMemcpyHostToDevice, c->stream));

@@ -303,6 +303,16 @@ __device__ __forceinline__ int energy_bin(const uint32_t* edges, int n, uint32_t
   return lo;
 }
 
+// Energy bin by bucket: the table gives, per bucket of the top bits of E, the bin of the
+// bucket's lower end; the few edges inside the bucket are then stepped over.  The same
+// result as energy_bin (the last edge <= E, or bin 0 below the first edge).
+__device__ __forceinline__ int energy_bin_b(const uint32_t* edges, const uint8_t* bkt, int n,
+                                            uint32_t E) {
+  int eb = bkt[E >> kEBucketShift];
+  while (eb + 1 < n && edges[eb + 1] <= E) ++eb;
+  return eb;
+}
+
 __device__ __forceinline__ int64_t count_mod(int64_t x, int64_t k, int64_t S) {
   // number of j in [0, x) with j % S == k
   return x > k ? (x - 1 - k) / S + 1 : 0;

@@ -37,6 +37,10 @@ constexpr int kMaxZEvery = 8;
 // Steps one launch of the step kernel may advance.
 constexpr int kMaxSub = 2;
 
+// Energy-bin lookup table: one entry per bucket of 2^22 energy units (the top 10 bits).
+constexpr int kEBucketShift = 22;
+constexpr int kEBuckets = 1 << (32 - kEBucketShift);
+
 // Device status bits.
 constexpr uint32_t kStOverflow = 1u;
 constexpr uint32_t kStHits = 2u;
@@ -82,6 +86,7 @@ struct StepArgs {
   const DevInst* inst;
   const int64_t* inj_cum;      // [n_inst][n_steps + 1] cumulative primaries per step
   const uint32_t* e_edges;
+  const uint8_t* e_bucket;     // [1024] bin of the lower end of each 2^22 energy bucket
   uint64_t* dens;
   int64_t* cur;
   int64_t* counters;           // [n_steps][kNC]

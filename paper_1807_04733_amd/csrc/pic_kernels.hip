@@ -47,16 +47,15 @@ __device__ __forceinline__ long long cur_fixed(double v, double mu) {
 
 // Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
 // sub-step (density per (z, E, spin), current per (z, spin)), or density to the global
-// bins when its slice does not fit in LDS.  `val` is cur_fixed(v, cos(theta)).
+// bins when its slice does not fit in LDS.  `eb` is the energy bin, `val` is
+// cur_fixed(v, cos(theta)).
 template <int MODE, int J>
 __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, unsigned char* dyn,
-                                          const uint32_t* s_edges, double z, uint32_t E,
-                                          uint32_t fl, long long val) {
+                                          double z, int eb, uint32_t fl, long long val) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
   if (a.sub_dens_on[J]) {
-    const int eb = a.n_ebins > 1 ? energy_bin(s_edges, a.n_ebins, E) : 0;
     const int idx = (zb * a.n_ebins + eb) * 2 + s;
     if (MODE & kModeDensGlobal) {
       const int64_t g = I.dens_off + (int64_t)a.sub_dens_slot[J] * I.nz * a.n_ebins * 2 + idx;
@@ -78,11 +77,18 @@ __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, u
     atomicAdd((unsigned long long*)(dyn + a.lds_cur_at[J]) + zb * 2 + s, (unsigned long long)val);
 }
 
+// energy bin of E for the density deposit (0 with a single bin)
+__device__ __forceinline__ int ebin(const StepArgs& a, const uint32_t* s_edges,
+                                    const uint8_t* s_ebkt, uint32_t E) {
+  return a.n_ebins > 1 ? energy_bin_b(s_edges, s_ebkt, a.n_ebins, E) : 0;
+}
+
 template <int MODE, int J>
 __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
-                                        const uint32_t* s_edges, double z, double mu, uint32_t E,
-                                        uint32_t fl, double v) {
-  deposit_v<MODE, J>(a, I, dyn, s_edges, z, E, fl, cur_fixed(v, mu));
+                                        const uint32_t* s_edges, const uint8_t* s_ebkt, double z,
+                                        double mu, uint32_t E, uint32_t fl, double v) {
+  const int eb = a.sub_dens_on[J] ? ebin(a, s_edges, s_ebkt, E) : 0;
+  deposit_v<MODE, J>(a, I, dyn, z, eb, fl, cur_fixed(v, mu));
 }
 
 // Merge sub-step J's LDS histogram slices of the workgroup's instance into the int64 bins
@@ -196,6 +202,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   __shared__ DevInst s_inst;
   __shared__ unsigned long long s_cnt[T][kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
+  __shared__ __align__(4) uint8_t s_ebkt[kEBuckets];
   __shared__ int s_slab, s_app, s_dead;
   __shared__ unsigned long long s_fast[T], s_left[T];
 
@@ -204,6 +211,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   const int wave = tid >> 6;
   for (int i = tid; i < a.lds_q_at / 4; i += blockDim.x) ((uint32_t*)dyn)[i] = 0;
   for (int i = tid; i < a.n_ebins; i += blockDim.x) s_edges[i] = a.e_edges[i];
+  for (int i = tid; i < kEBuckets / 4; i += blockDim.x)
+    ((uint32_t*)s_ebkt)[i] = ((const uint32_t*)a.e_bucket)[i];
   for (int i = tid; i < T * kNC; i += blockDim.x) (&s_cnt[0][0])[i] = 0;
   if (tid < T) {
     s_fast[tid] = 0;
@@ -320,7 +329,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
         if (!left) {
           const double zs = to_store<F>(ze);
-          deposit<MODE, J>(a, I, dyn, s_edges, zs, mu, E, fl, c.v);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v);
           lc[J].dep += 1;
           n_fast[J] += 1;
           if (a.sub_z_write[J]) {
@@ -419,7 +428,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
                           a.key1, hc, bad);
           z = to_store<F>(z);
-          deposit<MODE, J>(a, I, dyn, s_edges, z, mu, E, fl, c.v);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, z, mu, E, fl, c.v);
           lc[J].dep += 1;
         } else {
           z = to_store<F>(z);
@@ -522,7 +531,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0,
                         a.key1, h, bad);
         cz = to_store<F>(cz);
-        deposit<MODE, J>(a, I, dyn, s_edges, cz, cmu, cE, cfl, cc.v);
+        deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, cz, cmu, cE, cfl, cc.v);
         lc[J].dep += 1;
         lc[J].tr += h.tr;
         lc[J].ri += h.ri;
@@ -698,6 +707,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           // u01(w) < x  <=>  w + 0.5 < x 2^32  <=>  w < x 2^32 - 0.5 (both sides exact)
           const double thr = x * 0x1p32 - 0.5;
           const long long cv = cur_fixed(c.v, mu);
+          // energy bin once for both sub-steps (E does not change on the common path)
+          const int eb = (a.sub_dens_on[0] || a.sub_dens_on[T - 1]) ? ebin(a, s_edges, s_ebkt, rE) : 0;
 #pragma unroll
           for (int j = 0; j < T; ++j) {
             if (left_at < 0) {
@@ -711,9 +722,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                 left_at = j;
               } else {
                 z = to_store<F>(ze);
-                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, s_edges, z, rE, rfl, cv);
+                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, z, eb, rfl, cv);
                 if constexpr (T > 1)
-                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, s_edges, z, rE, rfl, cv);
+                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, z, eb, rfl, cv);
                 lc[j].dep += 1;
                 n_fast[j] += 1;
               }
