@@ -204,6 +204,7 @@ def variants_leg(prob, tuning: dict):
         "transparent_interfaces": dict(transparent=True),
         "no_secondaries": dict(secondaries=False),
         "energy_dependent_channels": dict(energy_tables=True),
+        "weighted_superparticles": dict(weights=True),
     }
     for name, kw in cases.items():
         sim = PicSim(W.variant(prob, **kw), device="cuda:0")

@@ -67,6 +67,10 @@ typedef enum {
 #define PIC_F_ABSORB_NEXT 16u  /* a carrier below E_min is removed at its next scattering
                                   event (Sec. III.A, lowest energy bin) instead of at once;
                                   every secondary is created */
+#define PIC_F_WEIGHTS     32u  /* weighted superparticles (Eq. 10): every primary takes a
+                                  weight from its instance's weight table at injection,
+                                  its secondaries inherit it, and the density, current and
+                                  generation moments are weighted sums */
 
 /* per-step counters returned by pic_counters(), [n_steps][PIC_NCOUNTERS] */
 enum {
@@ -81,6 +85,9 @@ enum {
   PIC_C_REFL_SURF,      /* vacuum-surface reflections */
   PIC_C_ALIVE,          /* carriers alive after the step (= sum of the step's density) */
   PIC_C_E_ABSORBED,     /* energy removed with absorbed carriers (fixed point) */
+  PIC_C_W_INJECTED,     /* sum of the weights of the primaries created, 2^-16 units
+                           (2^16 each without PIC_F_WEIGHTS); the normalisation of
+                           Eq. (10) is C = rho_exc / (this sum * 2^-16) */
   PIC_NCOUNTERS
 };
 
@@ -118,6 +125,14 @@ typedef struct {
   double   e_scale;                         /* 1/eV, > 0 when e_nodes > 0 */
   double   v_node[PIC_MAX_CHANNELS][PIC_MAX_TENTRIES];
   double   r_node[PIC_MAX_CHANNELS][PIC_MAX_TENTRIES];
+  /* Superparticle weights (Eq. 10; used with PIC_F_WEIGHTS).  w_nodes = 0: weight 1.
+   * w_nodes in 1..PIC_MAX_TENTRIES: a primary of spin s and initial energy E0 weighs the
+   * linear interpolation of w_node[s][.] at E0 (nodes at E = k / w_scale eV, clamped to
+   * the last; one node: a constant per spin), held as the integer rint(w 2^16).  Values
+   * in [2^-16, 2^15]. */
+  int32_t  w_nodes;
+  double   w_scale;                         /* 1/eV, in [0, 1e8] */
+  double   w_node[2][PIC_MAX_TENTRIES];
 } pic_instance;
 
 typedef struct {
@@ -142,7 +157,7 @@ typedef struct {
 
 /* Launch tuning.  Results never depend on it. */
 typedef struct {
-  int32_t block;          /* threads per workgroup: 64, 128, 256 or 512 */
+  int32_t block;          /* threads per workgroup: 64, 128, 256, 512 or 1024 */
   int32_t grid;           /* persistent workgroups per step launch; 0 = 2 x 256 CUs */
   int32_t compact_every;  /* launch the compaction pass every k steps; 0 = never */
   float   compact_frac;   /* compact a slab when dead slots exceed this fraction */
@@ -167,6 +182,7 @@ typedef struct {
   int32_t state_bytes;        /* 4 (binary32) or 8 (binary64) for z and mu */
   int32_t flags_spin_shift, flags_layer_shift, flags_layer_bits, flags_gen_shift;
   uint32_t flags_dead_bit;
+  int64_t off_w;              /* uint32 weights [capacity] in 2^-16 units, or -1 */
 } pic_layout;
 
 typedef struct pic_ctx pic_ctx;
@@ -194,14 +210,17 @@ pic_status pic_compact(pic_ctx* ctx);
 
 /* Convert the integer bins to binary64: dens_out [sum_i n_dslots*nz_i*NE*2] particle
  * counts and cur_out [sum_i n_cslots*nz_i*2] sum of v*cos(theta) in nm/fs; instances are
- * concatenated in order.  Device pointers (either may be NULL).  Enqueued, async. */
+ * concatenated in order.  With PIC_F_WEIGHTS both are weighted sums (the integer density
+ * bins hold weights in 2^-16 units, the current bins rint(v cos(theta) w 2^32) per
+ * carrier).  Device pointers (either may be NULL).  Enqueued, async. */
 pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
 
 /* Generation moment (context created with PIC_F_GEN_MOMENT): the sum of the generation
  * labels (1: primary, each secondary its parent's + 1, capped at 255) of the carriers
  * deposited in each density cell, per (density slot, depth, spin): gen_out
  * [sum_i n_dslots*nz_i*2], binary64 (exact integers), instances concatenated; divided by
- * the energy-summed density it is the mean generation map of Sec. V.  Device pointer.
+ * the energy-summed density it is the mean generation map of Sec. V.  With
+ * PIC_F_WEIGHTS the labels are weighted (sum of w * label, w in units of 1).  Device pointer.
  * Enqueued, async.  PIC_ESTATE without the flag. */
 pic_status pic_generations(pic_ctx* ctx, double* gen_out);
 

@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "pic_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 COUNTER_NAMES = ("injected", "ev_ee", "ev_el", "spawned", "absorbed", "sec_absorbed", "transmit",
-                 "refl_if", "refl_surf", "alive", "e_absorbed")
+                 "refl_if", "refl_surf", "alive", "e_absorbed", "w_injected")
 NCOUNTERS = len(COUNTER_NAMES)
 
 
@@ -50,6 +50,7 @@ class _Instance(C.Structure):
         ("nz", C.c_int32), ("inv_dz", C.c_double),
         ("e_nodes", C.c_int32), ("e_scale", C.c_double),
         ("v_node", C.POINTER(C.c_double)), ("r_node", C.POINTER(C.c_double)),
+        ("w_nodes", C.c_int32), ("w_scale", C.c_double), ("w_node", C.POINTER(C.c_double)),
     ]
 
 
@@ -61,7 +62,7 @@ class _Problem(C.Structure):
         ("n_ebins", C.c_int32), ("e_edges", C.POINTER(C.c_uint32)),
         ("dens_stride", C.c_int32), ("cur_stride", C.c_int32),
         ("root_lo", C.c_int64), ("root_hi", C.c_int64), ("n_threads", C.c_int32),
-        ("absorb_next", C.c_int32),
+        ("absorb_next", C.c_int32), ("weighted", C.c_int32),
     ]
 
 
@@ -75,6 +76,7 @@ class _Output(C.Structure):
         ("rec_layer", C.POINTER(C.c_int32)), ("rec_spin", C.POINTER(C.c_int32)),
         ("rec_gen", C.POINTER(C.c_int32)), ("rec_dead", C.POINTER(C.c_int32)),
         ("rec_inst", C.POINTER(C.c_int32)), ("rec_ev", C.POINTER(C.c_int32)),
+        ("rec_w", C.POINTER(C.c_uint32)),
         ("gen", C.POINTER(C.c_uint64)),
         ("g_dens", C.POINTER(C.c_double)), ("g_cur", C.POINTER(C.c_double)),
         ("grad", C.POINTER(C.c_double)), ("grad_per_tree", C.c_int32),
@@ -177,6 +179,10 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
             s.e_scale = float(it.e_scale)
             s.v_node = _ptr(arr(it.v_tab, np.float64), C.c_double)
             s.r_node = _ptr(arr(it.r_tab, np.float64), C.c_double)
+        if getattr(it, "w_tab", None) is not None:
+            s.w_nodes = int(it.w_tab.shape[1])
+            s.w_scale = float(it.w_scale)
+            s.w_node = _ptr(arr(it.w_tab, np.float64), C.c_double)
     P = _Problem()
     P.n_instances = len(problem.instances)
     P.inst = insts
@@ -194,6 +200,7 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
     P.root_lo, P.root_hi = (root_range if root_range is not None else (0, -1))
     P.n_threads = n_threads
     P.absorb_next = int(bool(getattr(problem, "absorb_next", False)))
+    P.weighted = int(bool(getattr(problem, "weighted", False)))
 
     nd = [int(np.prod(problem.dens_shape(i))) for i in range(len(problem.instances))]
     nc = [int(np.prod(problem.cur_shape(i))) for i in range(len(problem.instances))]
@@ -219,7 +226,8 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
                    mu=np.zeros(rec_cap), E=np.zeros(rec_cap, np.uint32),
                    layer=np.zeros(rec_cap, np.int32), spin=np.zeros(rec_cap, np.int32),
                    gen=np.zeros(rec_cap, np.int32), dead=np.zeros(rec_cap, np.int32),
-                   inst=np.zeros(rec_cap, np.int32), ev=np.zeros((rec_cap, 4), np.int32))
+                   inst=np.zeros(rec_cap, np.int32), ev=np.zeros((rec_cap, 4), np.int32),
+                   w=np.zeros(rec_cap, np.uint32))
         O.rec_cap = rec_cap
         O.rec_uid = _ptr(rec["uid"], C.c_uint64)
         O.rec_z = _ptr(rec["z"], C.c_double)
@@ -231,6 +239,7 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
         O.rec_dead = _ptr(rec["dead"], C.c_int32)
         O.rec_inst = _ptr(rec["inst"], C.c_int32)
         O.rec_ev = _ptr(rec["ev"], C.c_int32)
+        O.rec_w = _ptr(rec["w"], C.c_uint32)
     grad = None
     if g_dens is not None or g_cur is not None:
         inst0 = problem.instances[0]

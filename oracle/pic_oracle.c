@@ -87,6 +87,7 @@ typedef struct {
   uint32_t E;
   uint32_t root, lin;
   int layer, spin, gen;
+  uint32_t w;              /* superparticle weight, 2^-16 units (Eq. 10) */
   int ev[4];               /* events, transmissions, reflections, spawns */
   int dead;                /* absorption step or -1 */
   int n_next;              /* first step still to run */
@@ -329,7 +330,9 @@ static int energy_bin(const orc_problem* P, uint32_t E) {
 }
 
 /* Moments after the full step (Eqs. 16, 23): particle count per (depth, energy, spin)
- * and the sum of v cos(theta) per (depth, spin), in 2^-32 nm/fs fixed point. */
+ * and the sum of v cos(theta) per (depth, spin), in 2^-32 nm/fs fixed point.  Weighted
+ * superparticles (Eq. 10) add their weight instead of 1: w 2^16 to the density and
+ * rint(v cos(theta) w 2^32) to the current. */
 static void deposit(worker* W, particle* p, int n) {
   const orc_problem* P = W->P;
   const orc_instance* I = W->I;
@@ -341,20 +344,23 @@ static void deposit(worker* W, particle* p, int n) {
     const int eb = energy_bin(P, p->E);
     const int64_t idx = W->dens_off +
         (((int64_t)(n / P->dens_stride) * I->nz + zb) * P->n_ebins + eb) * 2 + p->spin;
+    const uint64_t add = P->weighted ? (uint64_t)p->w : 1u;
 #pragma omp atomic
-    W->O->dens[idx] += 1;
-    if (W->K && W->O->g_dens) g += W->O->g_dens[idx];
+    W->O->dens[idx] += add;
+    if (W->K && W->O->g_dens)
+      g += P->weighted ? W->O->g_dens[idx] * ((double)p->w * 0x1p-16) : W->O->g_dens[idx];
     if (W->O->gen) {
       /* mean generation map of Sec. V (Figs. 5, 7): the sum of the labels per cell, to be
        * divided by the cell's count */
       const int64_t gi = W->gen_off + ((int64_t)(n / P->dens_stride) * I->nz + zb) * 2 + p->spin;
 #pragma omp atomic
-      W->O->gen[gi] += (uint64_t)p->gen;
+      W->O->gen[gi] += (uint64_t)p->gen * add;
     }
   }
   if (n % P->cur_stride == 0) {
     const double vm = speed(I, p->layer, p->spin, p->E) * p->mu;
-    const int64_t val = llrint(vm * 4294967296.0);
+    const int64_t val =
+        P->weighted ? llrint((vm * (double)p->w) * 65536.0) : llrint(vm * 4294967296.0);
     const int64_t idx = W->cur_off + ((int64_t)(n / P->cur_stride) * I->nz + zb) * 2 + p->spin;
 #pragma omp atomic
     W->O->cur[idx] += val;
@@ -383,6 +389,7 @@ static void record(worker* W, const particle* p) {
   O->rec_gen[i] = p->gen;
   O->rec_dead[i] = p->dead;
   O->rec_inst[i] = W->inst_id;
+  if (O->rec_w) O->rec_w[i] = p->w;
   for (int k = 0; k < 4; ++k) O->rec_ev[i * 4 + k] = p->ev[k];
 }
 
@@ -413,6 +420,13 @@ static void run_particle(worker* W, particle* p) {
   record(W, p);
 }
 
+/* Weight of a primary of spin s and initial energy E0 (Eq. 10), 2^-16 units. */
+static uint32_t primary_weight(const orc_instance* I, int s, uint32_t E0) {
+  if (I->w_nodes <= 0) return 1u << 16;
+  const double w = node_interp(I->w_node + (int64_t)s * I->w_nodes, I->w_nodes, I->w_scale, E0);
+  return (uint32_t)llrint(w * 65536.0);
+}
+
 /* Source term, Eq. (17): one primary per root, created at the start of its step with a
  * depth from the pump profile, an isotropic direction, a spin and an energy. */
 static void run_root(worker* W, int64_t j, int n0) {
@@ -432,6 +446,7 @@ static void run_root(worker* W, int64_t j, int n0) {
   p.mu = stored(P, cosine(w[1]));
   p.spin = unif(w[2]) < I->src_up_frac ? 0 : 1;
   p.E = I->src_e_lo[p.spin] + (uint32_t)(((uint64_t)w[3] * (uint64_t)I->src_e_span[p.spin]) >> 32);
+  p.w = primary_weight(I, p.spin, p.E);
   p.layer = 0;
   for (int l = 0; l < I->n_layers; ++l)
     if (I->z_bound[l] <= p.z) p.layer = l;
@@ -443,6 +458,7 @@ static void run_root(worker* W, int64_t j, int n0) {
   p.newborn = 0;
   if (W->K && !W->O->grad_per_tree) p.S = (double*)calloc((size_t)W->K, sizeof(double));
   count(W, n0, ORC_C_INJECTED, 1);
+  count(W, n0, ORC_C_W_INJECTED, (int64_t)p.w);
   if (W->K && W->O->grad_per_tree) {
     memset(W->tree_score, 0, sizeof(double) * (size_t)W->K);
     W->tree_return = 0.0;
@@ -472,6 +488,10 @@ static int validate(const orc_problem* P) {
     if (I->root_offset + (uint64_t)tot > 0xFFFFFFFFull) return 1;
     if (P->inst[0].n_channels != I->n_channels || P->inst[0].n_ttables != I->n_ttables ||
         P->inst[0].t_entries != I->t_entries) return 1;
+    if (I->w_nodes < 0 || I->w_nodes > 64) return 1;
+    if (I->w_nodes > 0 && !(I->w_scale >= 0.0 && I->w_scale <= 1e8)) return 1;
+    for (int k = 0; k < 2 * I->w_nodes; ++k)
+      if (!(I->w_node[k] >= 0x1p-16 && I->w_node[k] <= 0x1p15)) return 1;
   }
   return 0;
 }

@@ -18,6 +18,7 @@ extern "C" {
 enum {
   ORC_C_INJECTED = 0, ORC_C_EV_EE, ORC_C_EV_EL, ORC_C_SPAWNED, ORC_C_ABSORBED,
   ORC_C_SEC_ABSORBED, ORC_C_TRANSMIT, ORC_C_REFL_IF, ORC_C_REFL_SURF, ORC_C_ALIVE, ORC_C_E_ABSORBED,
+  ORC_C_W_INJECTED,           /* sum of the primaries' weights, 2^-16 units (Eq. 10) */
   ORC_NCOUNTERS
 };
 
@@ -46,6 +47,13 @@ typedef struct {
   double e_scale;
   const double* v_node;       /* [C][e_nodes] nm/fs */
   const double* r_node;       /* [C][e_nodes] relative inelastic rate */
+  /* optional superparticle weights (Eq. 10): with w_nodes > 0 a primary of spin s and
+   * initial energy E0 carries the weight interpolated from w_node[s][.] (nodes at
+   * E = k / w_scale eV, clamped beyond the last), held as the integer rint(w 2^16); its
+   * secondaries inherit it.  w_nodes = 0: weight 1 */
+  int32_t w_nodes;
+  double w_scale;
+  const double* w_node;       /* [2][w_nodes] */
 } orc_instance;
 
 typedef struct {
@@ -66,6 +74,9 @@ typedef struct {
   int32_t absorb_next;        /* 0: a product below E_min is removed at once; 1: carriers
                                  below E_min live on and are removed at their next
                                  scattering event (Sec. III.A, lowest energy bin) */
+  int32_t weighted;           /* 1: the moments are sums over carriers of their weight
+                                 (density and generation label in 2^-16 units, current
+                                 rint(v cos(theta) w 2^32)); 0: plain counts */
 } orc_problem;
 
 typedef struct {
@@ -86,6 +97,7 @@ typedef struct {
   int32_t*  rec_dead;         /* step of absorption, -1 if alive at the end */
   int32_t*  rec_inst;
   int32_t*  rec_ev;           /* [4] per record: events, transmissions, reflections, spawns */
+  uint32_t* rec_w;            /* weight in 2^-16 units (may be NULL) */
   /* optional generation moment (NULL to skip): sum of the generation label (1: primary,
    * each secondary its parent's + 1) per (density slot, depth, spin), layout
    * [n_dslots][nz][2] per instance, instances concatenated; taken with the density */

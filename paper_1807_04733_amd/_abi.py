@@ -18,9 +18,10 @@ F_SECONDARIES = 2
 F_DEBUG = 4
 F_GEN_MOMENT = 8
 F_ABSORB_NEXT = 16
+F_WEIGHTS = 32
 
 COUNTER_NAMES = ("injected", "ev_ee", "ev_el", "spawned", "absorbed", "sec_absorbed",
-                 "transmit", "refl_if", "refl_surf", "alive", "e_absorbed")
+                 "transmit", "refl_if", "refl_surf", "alive", "e_absorbed", "w_injected")
 NCOUNTERS = len(COUNTER_NAMES)
 
 STATUS = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ENOMEM", 3: "PIC_ECAPACITY", 4: "PIC_EHIP",
@@ -54,6 +55,8 @@ class PicInstance(C.Structure):
         ("e_nodes", C.c_int32), ("e_scale", C.c_double),
         ("v_node", (C.c_double * MAX_TENTRIES) * MAX_CHANNELS),
         ("r_node", (C.c_double * MAX_TENTRIES) * MAX_CHANNELS),
+        ("w_nodes", C.c_int32), ("w_scale", C.c_double),
+        ("w_node", (C.c_double * MAX_TENTRIES) * 2),
     ]
 
 
@@ -87,6 +90,7 @@ class PicLayout(C.Structure):
         ("state_bytes", C.c_int32), ("flags_spin_shift", C.c_int32),
         ("flags_layer_shift", C.c_int32), ("flags_layer_bits", C.c_int32),
         ("flags_gen_shift", C.c_int32), ("flags_dead_bit", C.c_uint32),
+        ("off_w", C.c_int64),
     ]
 
 

@@ -122,9 +122,11 @@ struct HitScore {
 
 // Deposit weight of a carrier at the end of step n: g of its density bin (weight 1) plus
 // g of its current bin times v*cos(theta) (the fixed-point value the forward deposits).
+// Weighted superparticles (Eq. 10) deposit their weight w (wfx in 2^-16 units): the
+// density term is g w and the current value rint(v cos(theta) w 2^32).
 __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst& I,
                                                  const double* et, double z, double mu, uint32_t E,
-                                                 uint32_t fl, const uint32_t* s_edges,
+                                                 uint32_t fl, uint32_t wfx, const uint32_t* s_edges,
                                                  const double* s_gcur) {
   const StepArgs& a = A.s;
   int zb = (int)floor(z * I.inv_dz);
@@ -133,14 +135,15 @@ __device__ __forceinline__ double deposit_weight(const AdjArgs& A, const DevInst
   double g = 0.0;
   if (a.dens_on && A.g_dens) {
     const int eb = a.n_ebins > 1 ? energy_bin(s_edges, a.n_ebins, E) : 0;
-    g += A.g_dens[I.dens_off + (((int64_t)a.dens_slot * I.nz + zb) * a.n_ebins + eb) * 2 + s];
+    const double gd =
+        A.g_dens[I.dens_off + (((int64_t)a.dens_slot * I.nz + zb) * a.n_ebins + eb) * 2 + s];
+    g += a.wt ? gd * ((double)wfx * 0x1p-16) : gd;
   }
   if (a.cur_on && A.g_cur) {
     const double gc = s_gcur[zb * 2 + s];
     if (gc != 0.0) {
-      const double vm = speed_at(I, et, layer_of(fl), s, E) * mu;
-      const double sh = vm * 4294967296.0 + 0x1.8p52;
-      const long long val = __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+      const double v = speed_at(I, et, layer_of(fl), s, E);
+      const long long val = a.wt ? cur_fixed_w(v, mu, wfx) : cur_fixed(v, mu);
       g += gc * ((double)val * 0x1p-32);
     }
   }
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
     // The whole replayed step of one carrier with its score terms.  All lanes of the wave
     // call it together; lanes with nothing to do pass a dead carrier.
     auto general = [&](bool is_new, int64_t gi, double z, double mu, uint32_t E, uint32_t fl,
-                       uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
+                       uint32_t lo, uint32_t hi, uint32_t wfx) __attribute__((always_inline)) {
       const bool alive0 = !(fl & kDead);
       bool died = false;
       AdjLane L{gi, lo, 0.0, false};
@@ -318,13 +321,14 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
                             chc, bad, et, hs);
                 }
                 cz = to_store<F>(cz);
-                const double g = deposit_weight(A, I, et, cz, cmu, E2, cfl, s_edges, s_gcur);
+                const double g = deposit_weight(A, I, et, cz, cmu, E2, cfl, wfx, s_edges, s_gcur);
                 on_deposit<ADJ>(ops, a, I, et, CL, cfl, E2, g, step);
                 gz[cg] = (F)cz;
                 gmu[cg] = (F)cmu;
                 a.E[cg] = E2;
                 a.uid[cg] = (uint64_t)lo | ((uint64_t)lin << 32);
                 a.flags[cg] = cfl;
+                if (a.wt) a.wt[cg] = wfx;  // a secondary carries its parent's weight
               } else {
                 atomicOr(a.status, kStOverflow);
               }
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
                       hs);
           }
           z = to_store<F>(z);
-          const double g = deposit_weight(A, I, et, z, mu, E, fl, s_edges, s_gcur);
+          const double g = deposit_weight(A, I, et, z, mu, E, fl, wfx, s_edges, s_gcur);
           on_deposit<ADJ>(ops, a, I, et, L, fl, E, g, step);
         } else {
           z = to_store<F>(z);
@@ -380,10 +384,11 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       const uint32_t t = act ? SQ[sn - n + lane] : 0u;
       sn -= n;
       const int64_t g = base + t;
-      uint32_t fl = kDead, E = 0, lo = 0, hi = 0;
+      uint32_t fl = kDead, E = 0, lo = 0, hi = 0, wfx = 1u << 16;
       double z = 0.0, mu = 0.0;
       if (act) {
         fl = a.flags[g];
+        if (a.wt) wfx = a.wt[g];
         z = (double)gz[g];
         mu = (double)gmu[g];
         E = a.E[g];
@@ -396,13 +401,13 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
           z = replay_flights<F>(z, (v * mu) * a.h, d);
         }
       }
-      general(false, g, z, mu, E, fl, lo, hi);
+      general(false, g, z, mu, E, fl, lo, hi, wfx);
       wave_sync();
     };
 
     // next slot of this lane, fetched one iteration ahead (as in the forward step)
     F nz = 0, nmu = 0;
-    uint32_t nE = 0, nfl = kDead;
+    uint32_t nE = 0, nfl = kDead, nw = 1u << 16;
     uint64_t nu = 0;
     auto fetch = [&](int t) {
       if (t < tail0) {
@@ -412,6 +417,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         nmu = gmu[g];
         nE = a.E[g];
         nu = a.uid[g];
+        if (a.wt) nw = a.wt[g];
       } else {
         nfl = kDead;
       }
@@ -420,7 +426,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
     for (int tb = wave * 64; tb < total; tb += blockDim.x) {
       const int t = tb + lane;
       const F rz = nz, rmu = nmu;
-      const uint32_t rE = nE, rfl = nfl;
+      const uint32_t rE = nE, rfl = nfl, rw = nw;
       const uint64_t ru = nu;
       fetch(t + (int)blockDim.x);
       const bool have = t < total;
@@ -447,7 +453,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
           const double zs = to_store<F>(ze);
           const int64_t gi = base + t;
           if (ADJ != 3) {
-            const double g = deposit_weight(A, I, et, zs, mu, rE, rfl, s_edges, s_gcur);
+            const double g = deposit_weight(A, I, et, zs, mu, rE, rfl, rw, s_edges, s_gcur);
             if (ADJ == 1 && g != 0.0) slow = true;
             if (ADJ == 2 && g != 0.0) A.r[gi] += g;
           }
@@ -462,7 +468,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         const int newpos = append_slot(is_new, &s_app, tail0);
         int64_t gi = base + t;
         double z = 0.0, mu = 0.0;
-        uint32_t E = 0, fl = kDead, lo = 0;
+        uint32_t E = 0, fl = kDead, lo = 0, wfx = 1u << 16;
         if (is_new) {
           gi = base + newpos;
           if (newpos >= cap) {
@@ -485,12 +491,16 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
               if (I.lay[q].x <= z) l = q;
             fl = with_nf(s | ((uint32_t)l << kLayerShift) | (1u << kGenShift), step);
             lo = root;
+            if (a.wt) {
+              wfx = primary_weight(I, a.etab + I.etab_off + 2 * (int)I.n_ch * I.e_nodes, (int)s, E);
+              a.wt[gi] = wfx;
+            }
             if (ADJ == 1)
               for (int k = 0; k < A.K; ++k) A.S[gi * A.K + k] = 0.0;
             if (ADJ == 2) A.r[gi] = 0.0;
           }
         }
-        general(is_new && newpos < cap, gi, z, mu, E, fl, lo, 0u);
+        general(is_new && newpos < cap, gi, z, mu, E, fl, lo, 0u, wfx);
       }
       // ---- queue the general-path slots
       const uint64_t ms = __ballot(slow);

@@ -52,7 +52,7 @@ struct Plan {
   int64_t off_z, off_mu, off_E, off_uid, off_flags, off_ev;
   int64_t off_slab_base, off_slab_cap, off_slab_tail, off_slab_dead, off_slab_inst, off_slab_k;
   int64_t off_inst, off_inj, off_edges, off_dens, off_cur, off_counters, off_queue, off_status;
-  int64_t off_stats, off_gen = -1, off_etab = -1;
+  int64_t off_stats, off_gen = -1, off_etab = -1, off_w = -1;
   int64_t off_grad = -1, off_S = -1, off_r = -1, off_R = -1;
   int K = 0;
   int64_t n_roots = 0;
@@ -112,6 +112,16 @@ pic_status validate(const pic_config* c) {
     for (int t = 0; t < I.n_ttables; ++t)
       for (int e = 0; e < I.t_entries; ++e)
         if (!(I.T[t][e] >= 0.0 && I.T[t][e] <= 1.0)) return fail(PIC_EINVAL, w + "T outside [0,1]");
+    if (c->flags & PIC_F_WEIGHTS) {
+      if (I.w_nodes < 0 || I.w_nodes > PIC_MAX_TENTRIES)
+        return fail(PIC_EINVAL, w + "w_nodes must be 0..PIC_MAX_TENTRIES");
+      if (I.w_nodes && !(I.w_scale >= 0.0 && I.w_scale <= 1e8))
+        return fail(PIC_EINVAL, w + "w_scale must be in [0, 1e8]");
+      for (int s = 0; s < 2; ++s)
+        for (int k = 0; k < I.w_nodes; ++k)
+          if (!(I.w_node[s][k] >= 0x1p-16 && I.w_node[s][k] <= 0x1p15))
+            return fail(PIC_EINVAL, w + "weights must be in [2^-16, 2^15]");
+    }
     if (I.t_entries > 1 && (!(I.T_scale > 0.0) || !(I.T_scale <= 1e8)))
       return fail(PIC_EINVAL, w + "T_scale must be in (0, 1e8]");
     if (!(I.src_z_lo >= I.z_bound[0] && I.src_z_hi <= I.z_bound[I.n_layers] && I.src_z_lo <= I.src_z_hi))
@@ -184,7 +194,9 @@ Plan make_plan(const pic_config* c) {
     p.gen_off.push_back(p.gen_len);
     p.etab_off.push_back(p.etab_len);
     const int et_words = 2 * I.n_channels * I.e_nodes;
-    p.etab_len += et_words;
+    // weight rows [2][w_nodes] follow the instance's energy tables (read at injection)
+    const int w_words = (c->flags & PIC_F_WEIGHTS) ? 2 * I.w_nodes : 0;
+    p.etab_len += et_words + w_words;
     p.etab_max = std::max(p.etab_max, et_words);
     p.dens_len += (int64_t)p.n_dslots * I.nz * c->n_ebins * 2;
     p.cur_len += (int64_t)p.n_cslots * I.nz * 2;
@@ -220,6 +232,7 @@ Plan make_plan(const pic_config* c) {
   p.off_stats = take((int64_t)c->n_steps * 2 * 8);
   if (c->flags & PIC_F_GEN_MOMENT) p.off_gen = take(p.gen_len * 8);
   if (p.etab_len > 0) p.off_etab = take(p.etab_len * 8);
+  if (c->flags & PIC_F_WEIGHTS) p.off_w = take(C * 4);
   if (c->adjoint) {
     const pic_instance& I0 = c->inst[0];
     p.K = I0.n_channels + I0.n_ttables * I0.t_entries;
@@ -286,6 +299,10 @@ void drop_graph(pic_ctx* c) {
   c->g_start = c->g_n = -1;
 }
 
+// bytes per entry of the LDS density and generation slices: u64 sums of weights in a
+// weighted run, u32 counts otherwise
+size_t dens_elem(const pic_ctx* c) { return c->plan.off_w >= 0 ? 8 : 4; }
+
 // Dynamic LDS layout of one step launch over n_sub sub-steps: the density slices (of the
 // sub-steps that deposit density, when density goes to LDS), the current slices, then the
 // per-wave queues.  Fills the offsets in `a` (if given) and returns the bytes.
@@ -295,7 +312,7 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
   for (int j = 0; j < kMaxSub; ++j) {
     const bool d = j < n_sub && dens_on[j] && c->dens_lds;
     if (a) a->lds_dens_at[j] = d ? (int32_t)off : -1;
-    if (d) off = (off + (size_t)c->lds_dens_words * 4 + 15) & ~(size_t)15;
+    if (d) off = (off + (size_t)c->lds_dens_words * dens_elem(c) + 15) & ~(size_t)15;
   }
   for (int j = 0; j < kMaxSub; ++j) {
     const bool u = j < n_sub && cur_on[j];
@@ -306,7 +323,7 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
   for (int j = 0; j < kMaxSub; ++j) {
     const bool g = j < n_sub && dens_on[j] && c->dens_lds && c->plan.off_gen >= 0;
     if (a) a->lds_gen_at[j] = g ? (int32_t)off : -1;
-    if (g) off = (off + (size_t)c->lds_cur_words * 4 + 15) & ~(size_t)15;
+    if (g) off = (off + (size_t)c->lds_cur_words * dens_elem(c) + 15) & ~(size_t)15;
   }
   // the energy tables of the workgroup's instance
   if (a) a->lds_etab_at = c->plan.etab_max ? (int32_t)off : -1;
@@ -370,6 +387,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.gen = c->at<uint64_t>(p.off_gen);
   a.etab = c->at<double>(p.off_etab);
   a.etab_words = p.etab_max;
+  a.wt = c->at<uint32_t>(p.off_w);
   a.lds_etab_at = -1;
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
@@ -416,6 +434,7 @@ CompactArgs compact_args(const pic_ctx* c) {
   a.S = nullptr;
   a.K = 0;
   a.r = nullptr;
+  a.w = c->at<uint32_t>(p.off_w);
   return a;
 }
 
@@ -519,6 +538,13 @@ pic_status upload_tables(pic_ctx* c) {
         c->h_etab[p.etab_off[i] + (int64_t)ch * I.e_nodes + k] = I.v_node[ch][k];
         c->h_etab[p.etab_off[i] + (int64_t)(I.n_channels + ch) * I.e_nodes + k] = I.r_node[ch][k];
       }
+    const bool wtd = (cfg.flags & PIC_F_WEIGHTS) != 0;
+    D.w_nodes = wtd ? I.w_nodes : 0;
+    D.w_scale = wtd ? I.w_scale : 0.0;
+    for (int s = 0; s < 2 && wtd; ++s)
+      for (int k = 0; k < I.w_nodes; ++k)
+        c->h_etab[p.etab_off[i] + 2 * (int64_t)I.n_channels * I.e_nodes + s * I.w_nodes + k] =
+            I.w_node[s][k];
     D.T_scale = I.T_scale;
     D.inv_dz = I.inv_dz;
     D.src_lo = I.src_z_lo;
@@ -728,7 +754,7 @@ pic_status pic_deposit(pic_ctx* c, double* dens_out, double* cur_out) {
   if (!c) return fail(PIC_EINVAL, "null context");
   HIP_TRY(launch_convert(c->at<uint64_t>(c->plan.off_dens), dens_out ? c->plan.dens_len : 0,
                          c->at<int64_t>(c->plan.off_cur), cur_out ? c->plan.cur_len : 0, dens_out,
-                         cur_out, c->stream));
+                         cur_out, c->plan.off_w >= 0 ? 0x1p-16 : 1.0, c->stream));
   return PIC_OK;
 }
 
@@ -736,7 +762,7 @@ pic_status pic_generations(pic_ctx* c, double* gen_out) {
   if (!c || !gen_out) return fail(PIC_EINVAL, "null argument");
   if (c->plan.off_gen < 0) return fail(PIC_ESTATE, "context created without PIC_F_GEN_MOMENT");
   HIP_TRY(launch_convert(c->at<uint64_t>(c->plan.off_gen), c->plan.gen_len, nullptr, 0, gen_out,
-                         nullptr, c->stream));
+                         nullptr, c->plan.off_w >= 0 ? 0x1p-16 : 1.0, c->stream));
   return PIC_OK;
 }
 
@@ -762,7 +788,8 @@ pic_status pic_reset(pic_ctx* c) {
 pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (!c || !t) return fail(PIC_EINVAL, "null argument");
   const int b = t->block;
-  if (!(b == 64 || b == 128 || b == 256 || b == 512)) return fail(PIC_EINVAL, "block must be 64, 128, 256 or 512");
+  if (!(b == 64 || b == 128 || b == 256 || b == 512 || b == 1024))
+    return fail(PIC_EINVAL, "block must be 64, 128, 256, 512 or 1024");
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
   if (t->z_every < 1 || t->z_every > kMaxZEvery) return fail(PIC_EINVAL, "z_every must be 1..8");
@@ -807,6 +834,7 @@ pic_status pic_layout_of(const pic_ctx* c, pic_layout* o) {
   o->flags_layer_bits = 4;
   o->flags_gen_shift = kGenShift;
   o->flags_dead_bit = kDead;
+  o->off_w = p.off_w;
   return PIC_OK;
 }
 
@@ -953,7 +981,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   float best_ms = 1e30f;
   pic_tuning win = cur;
   // stage 1: workgroup size and persistent grid
-  for (int block : {128, 256, 512}) {
+  for (int block : {128, 256, 512, 1024}) {
     if (lds_for(c, block) > c->max_lds) continue;
     for (int grid : {256, 512, 1024, 2048}) {
       pic_tuning t = cur;

@@ -100,6 +100,31 @@ __device__ __forceinline__ double inel_rate_at(const DevInst& I, const double* e
   return Ek * I.chan[l][s].y;
 }
 
+// Weight of a primary of spin s and initial energy E0 (Eq. 10) in 2^-16 units: the
+// interpolation of the spin's row of the instance's weight table (`wrows`, [2][w_nodes]),
+// rounded to nearest even; 2^16 without a table.
+__device__ __forceinline__ uint32_t primary_weight(const DevInst& I, const double* wrows, int s,
+                                                   uint32_t E0) {
+  if (!I.w_nodes) return 1u << 16;
+  const double w = node_interp(wrows + s * I.w_nodes, I.w_nodes, I.w_scale, E0);
+  return (uint32_t)(long long)rint(w * 65536.0);
+}
+
+// v cos(theta) of the current moment in 2^-32 nm/fs fixed point, rounded half to even:
+// adding 1.5*2^52 (|x| < 2^51) leaves the integer in the low mantissa bits, identical to
+// rint().  A weighted carrier (wfx in 2^-16 units, `weighted`) adds rint(v mu w 2^32),
+// computed as (v mu wfx) 2^16.
+__device__ __forceinline__ long long cur_fixed(double v, double mu) {
+  const double vm = v * mu;
+  const double sh = vm * 4294967296.0 + 0x1.8p52;
+  return __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+}
+__device__ __forceinline__ long long cur_fixed_w(double v, double mu, uint32_t wfx) {
+  const double vm = v * mu;
+  const double sh = (vm * (double)wfx) * 65536.0 + 0x1.8p52;
+  return __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+}
+
 struct HitCounts {
   uint32_t tr, ri, rs;
 };

@@ -53,6 +53,7 @@ struct alignas(32) DevInst {
   double T_scale, inv_dz;
   double src_lo, src_hi, src_lambda, src_cd, src_up;
   double e_scale;              // energy tables: nodes at E = k / e_scale eV
+  double w_scale;              // weight table: nodes at E = k / w_scale eV
   uint32_t e_lo[2], e_span[2];
   int32_t n_layers, t_entries, nz, n_slabs;
   uint64_t root_offset;
@@ -60,6 +61,8 @@ struct alignas(32) DevInst {
   int64_t gen_off;             // ... in the generation-moment bins
   int64_t etab_off;            // ... in the energy tables ([v rows | rate rows][channel][node])
   int32_t slab0, e_nodes;      // e_nodes = 0: constant speeds and rates
+  int32_t w_nodes, pad1;       // weight table nodes per spin (0: weight 1); rows [2][w_nodes]
+                               // follow the energy tables at etab_off + 2 n_ch e_nodes
   uint8_t tt[kMaxL - 1][2][2]; // transmission table per (interface, direction, spin)
   uint8_t chi[kMaxL][2];       // channel index per (layer, spin) (adjoint parameter slot)
   uint8_t n_ch;                // channels (rows of each energy table)
@@ -128,6 +131,8 @@ struct StepArgs {
   // instance into dynamic LDS at lds_etab_at (step kernel; etab_words doubles at most)
   const double* etab;
   int32_t lds_etab_at, etab_words;
+  // superparticle weights (2^-16 units) per slot, or null: the moments are plain counts
+  uint32_t* wt;
 };
 
 struct AdjArgs {
@@ -156,11 +161,12 @@ struct CompactArgs {
   double* S;                   // adjoint score rows [capacity][K] moved along, or null
   int32_t K;
   double* r;                   // adjoint partial returns moved along, or null
+  uint32_t* w;                 // superparticle weights moved along, or null
 };
 
 // bytes of one wave's newborn queue (step kernel) and general-path slot queue (adjoint
 // replay) in dynamic LDS
-constexpr size_t kChildQueueBytes = 64 * (8 + 4 * 4);
+constexpr size_t kChildQueueBytes = 64 * (8 + 4 * 5);
 constexpr size_t kSlowQueueBytes = 128 * 4;
 // bytes of one wave's queues in the step kernel: newborns, then the slot queues of
 // sub-step 0 (128 entries) and, in two-step launches, of sub-step 1 (256 entries)
@@ -186,6 +192,6 @@ size_t step_static_lds();
 hipError_t set_step_lds_limit(size_t bytes);
 hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
-                          double* dout, double* cout, hipStream_t s);
+                          double* dout, double* cout, double dscale, hipStream_t s);
 
 }  // namespace pic

@@ -28,7 +28,8 @@ namespace pic {
 // Compile-time launch modes of the step kernel.
 constexpr int kModeDebug = 1;       // keep per-particle event counts
 constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slice does not fit)
-constexpr int kModeETab = 8;        // energy-dependent speeds and rates (tables in LDS)
+constexpr int kModeExt = 8;         // energy-dependent speeds and rates (tables in LDS) and / or
+                                    // weighted superparticles (StepArgs::wt)
 
 // Compile-time sub-step index for the generic lambdas of k_step.
 template <int V>
@@ -36,30 +37,32 @@ struct Sub {
   static constexpr int value = V;
 };
 
-// v cos(theta) of the current moment in 2^-32 nm/fs fixed point, rounded half to even:
-// adding 1.5*2^52 (|v mu 2^32| < 2^51) leaves the integer in the low mantissa bits,
-// identical to rint()
-__device__ __forceinline__ long long cur_fixed(double v, double mu) {
-  const double vm = v * mu;
-  const double sh = vm * 4294967296.0 + 0x1.8p52;
-  return __double_as_longlong(sh) - __double_as_longlong(0x1.8p52);
+// weighted moments: the density and generation slices hold u64 sums of weights
+template <int MODE>
+__device__ __forceinline__ bool weighted(const StepArgs& a) {
+  return (MODE & kModeExt) && a.wt != nullptr;
 }
 
 // Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
 // sub-step (density per (z, E, spin), current per (z, spin)), or density to the global
-// bins when its slice does not fit in LDS.  `eb` is the energy bin, `val` is
-// cur_fixed(v, cos(theta)).
+// bins when its slice does not fit in LDS.  `eb` is the energy bin, `val` the current
+// value (cur_fixed / cur_fixed_w), `wfx` the weight (2^-16 units) of a weighted run.
 template <int MODE, int J>
 __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, unsigned char* dyn,
-                                          double z, int eb, uint32_t fl, long long val) {
+                                          double z, int eb, uint32_t fl, long long val,
+                                          uint32_t wfx) {
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
   if (a.sub_dens_on[J]) {
     const int idx = (zb * a.n_ebins + eb) * 2 + s;
+    const bool wtd = weighted<MODE>(a);
+    const unsigned long long add = wtd ? (unsigned long long)wfx : 1ull;
     if (MODE & kModeDensGlobal) {
       const int64_t g = I.dens_off + (int64_t)a.sub_dens_slot[J] * I.nz * a.n_ebins * 2 + idx;
-      atomicAdd((unsigned long long*)&a.dens[g], 1ull);
+      atomicAdd((unsigned long long*)&a.dens[g], add);
+    } else if (wtd) {
+      atomicAdd((unsigned long long*)(dyn + a.lds_dens_at[J]) + idx, add);
     } else {
       atomicAdd((uint32_t*)(dyn + a.lds_dens_at[J]) + idx, 1u);
     }
@@ -67,7 +70,10 @@ __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, u
       const uint32_t gl = (fl >> kGenShift) & kGenMask;
       if (MODE & kModeDensGlobal) {
         const int64_t g = I.gen_off + ((int64_t)a.sub_dens_slot[J] * I.nz + zb) * 2 + s;
-        atomicAdd((unsigned long long*)&a.gen[g], (unsigned long long)gl);
+        atomicAdd((unsigned long long*)&a.gen[g], (unsigned long long)gl * add);
+      } else if (wtd) {
+        atomicAdd((unsigned long long*)(dyn + a.lds_gen_at[J]) + zb * 2 + s,
+                  (unsigned long long)gl * add);
       } else {
         atomicAdd((uint32_t*)(dyn + a.lds_gen_at[J]) + zb * 2 + s, gl);
       }
@@ -83,56 +89,58 @@ __device__ __forceinline__ int ebin(const StepArgs& a, const uint32_t* s_edges,
   return a.n_ebins > 1 ? energy_bin_b(s_edges, s_ebkt, a.n_ebins, E) : 0;
 }
 
+// current value of a carrier (weighted in a weighted run)
+template <int MODE>
+__device__ __forceinline__ long long cur_val(const StepArgs& a, double v, double mu,
+                                             uint32_t wfx) {
+  return weighted<MODE>(a) ? cur_fixed_w(v, mu, wfx) : cur_fixed(v, mu);
+}
+
 template <int MODE, int J>
 __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
                                         const uint32_t* s_edges, const uint8_t* s_ebkt, double z,
-                                        double mu, uint32_t E, uint32_t fl, double v) {
+                                        double mu, uint32_t E, uint32_t fl, double v,
+                                        uint32_t wfx) {
   const int eb = a.sub_dens_on[J] ? ebin(a, s_edges, s_ebkt, E) : 0;
-  deposit_v<MODE, J>(a, I, dyn, z, eb, fl, cur_fixed(v, mu));
+  deposit_v<MODE, J>(a, I, dyn, z, eb, fl, cur_val<MODE>(a, v, mu, wfx), wfx);
+}
+
+// Merge one LDS histogram slice of n entries (u32 or u64) into int64 bins (non-zero
+// entries only) and clear it.
+template <typename U>
+__device__ __forceinline__ void merge_slice(U* s, unsigned long long* g, int n) {
+  for (int b = threadIdx.x; b < n; b += blockDim.x) {
+    const U v = s[b];
+    if (v) {
+      atomicAdd(&g[b], (unsigned long long)v);
+      s[b] = 0;
+    }
+  }
 }
 
 // Merge sub-step J's LDS histogram slices of the workgroup's instance into the int64 bins
-// (non-zero entries only) and clear them.
+// and clear them.
 template <int MODE, int J>
 __device__ void flush_bins(const StepArgs& a, const DevInst& I, unsigned char* dyn) {
   if (!(MODE & kModeDensGlobal) && a.sub_dens_on[J]) {
-    uint32_t* s_dens = (uint32_t*)(dyn + a.lds_dens_at[J]);
+    const bool wtd = weighted<MODE>(a);
     const int n = I.nz * a.n_ebins * 2;
     unsigned long long* g =
         (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.sub_dens_slot[J] * n);
-    for (int b = threadIdx.x; b < n; b += blockDim.x) {
-      const uint32_t v = s_dens[b];
-      if (v) {
-        atomicAdd(&g[b], (unsigned long long)v);
-        s_dens[b] = 0;
-      }
-    }
+    if (wtd) merge_slice((unsigned long long*)(dyn + a.lds_dens_at[J]), g, n);
+    else merge_slice((uint32_t*)(dyn + a.lds_dens_at[J]), g, n);
     if (a.gen) {
-      uint32_t* s_gen = (uint32_t*)(dyn + a.lds_gen_at[J]);
       const int m = I.nz * 2;
       unsigned long long* gg =
           (unsigned long long*)(a.gen + I.gen_off + (int64_t)a.sub_dens_slot[J] * m);
-      for (int b = threadIdx.x; b < m; b += blockDim.x) {
-        const uint32_t v = s_gen[b];
-        if (v) {
-          atomicAdd(&gg[b], (unsigned long long)v);
-          s_gen[b] = 0;
-        }
-      }
+      if (wtd) merge_slice((unsigned long long*)(dyn + a.lds_gen_at[J]), gg, m);
+      else merge_slice((uint32_t*)(dyn + a.lds_gen_at[J]), gg, m);
     }
   }
   if (a.sub_cur_on[J]) {
-    unsigned long long* s_cur = (unsigned long long*)(dyn + a.lds_cur_at[J]);
     const int n = I.nz * 2;
-    unsigned long long* g =
-        (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.sub_cur_slot[J] * n);
-    for (int b = threadIdx.x; b < n; b += blockDim.x) {
-      const unsigned long long v = s_cur[b];
-      if (v) {
-        atomicAdd(&g[b], v);
-        s_cur[b] = 0;
-      }
-    }
+    merge_slice((unsigned long long*)(dyn + a.lds_cur_at[J]),
+                (unsigned long long*)(a.cur + I.cur_off + (int64_t)a.sub_cur_slot[J] * n), n);
   }
 }
 
@@ -150,7 +158,7 @@ __device__ void flush_all(const StepArgs& a, const DevInst& I, unsigned char* dy
 constexpr int kQ = 64;
 struct ChildQueue {  // kChildQueueBytes
   double z[kQ];
-  uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ];
+  uint32_t lo[kQ], hi[kQ], E[kQ], fl[kQ], w[kQ];
 };
 
 // The SoA arrays offset to one slab: uniform base pointers with 32-bit lane offsets.
@@ -162,6 +170,7 @@ struct SlabPtrs {
   uint64_t* uid;
   uint32_t* fl;
   uint64_t* ev;
+  uint32_t* w;
 };
 
 // Element i of a slab array, addressed with a 32-bit byte offset from the slab's base
@@ -193,9 +202,9 @@ constexpr int kSlowQ1 = 256;
 // way.  New primaries (source term, Eq. 17) of a sub-step are appended with their initial
 // state and queued for its general path.
 template <typename F, int T, int MODE>
-__global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
+__global__ void __launch_bounds__(1024, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  constexpr bool ET = (MODE & kModeETab) != 0;
+  constexpr bool ET = (MODE & kModeExt) != 0;
   // dynamic LDS: [histogram slices of the sub-steps | energy tables | per wave: newborn
   // queue, slot queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -232,6 +241,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   const double* const et = ET ? (const double*)(dyn + a.lds_etab_at) : nullptr;
   const bool tau2 = a.tau_exp2 != 0;
+  const bool WT = weighted<MODE>(a);
+  constexpr uint32_t kW1 = 1u << 16;  // weight 1
   int cur_inst = -1;
   bool bad = false;
 
@@ -279,9 +290,15 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       if (n_inj0) atomicAdd(&s_cnt[0][PIC_C_INJECTED], (unsigned long long)n_inj0);
       if constexpr (T > 1)
         if (n_inj1) atomicAdd(&s_cnt[T - 1][PIC_C_INJECTED], (unsigned long long)n_inj1);
+      if (!WT) {  // weight 1 each (weighted primaries add theirs at injection)
+        if (n_inj0) atomicAdd(&s_cnt[0][PIC_C_W_INJECTED], (unsigned long long)n_inj0 << 16);
+        if constexpr (T > 1)
+          if (n_inj1)
+            atomicAdd(&s_cnt[T - 1][PIC_C_W_INJECTED], (unsigned long long)n_inj1 << 16);
+      }
     }
     const SlabPtrs<F> sp{gz + base, gmu + base, a.E + base, a.uid + base, a.flags + base,
-                         DEBUG ? a.ev + base : nullptr};
+                         DEBUG ? a.ev + base : nullptr, WT ? a.wt + base : nullptr};
     LaneCounts lc[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) lc[j] = LaneCounts{0, 0, 0, 0};
@@ -315,7 +332,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // needed), or the slot goes to the sub-step's queue.  `slot` holds the carrier whose
     // stored z is that position (stamp = this sub-step's phase).
     auto cont = [&](auto sub, bool act, uint32_t slot, double z, double mu, uint32_t E,
-                    uint32_t fl, uint32_t lo, uint32_t hi) __attribute__((always_inline)) {
+                    uint32_t fl, uint32_t lo, uint32_t hi, uint32_t wfx)
+                    __attribute__((always_inline)) {
       constexpr int J = decltype(sub)::value;
       bool left = false;
       if (act) {
@@ -329,7 +347,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
         if (!left) {
           const double zs = to_store<F>(ze);
-          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v, wfx);
           lc[J].dep += 1;
           n_fast[J] += 1;
           if (a.sub_z_write[J]) {
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // the step, with its state and its slot.
     auto general = [&](auto sub, bool from_soa, bool is_new, uint32_t gi, double& z, double& mu,
                        uint32_t& E, uint32_t& fl, uint32_t lo, uint32_t hi, uint64_t evp,
-                       uint32_t& slot) __attribute__((always_inline)) -> bool {
+                       uint32_t wfx, uint32_t& slot) __attribute__((always_inline)) -> bool {
       constexpr int J = decltype(sub)::value;
       const uint32_t step = step0 + J;
       // stamp of the z this sub-step stores (0 when it ends a write-back period)
@@ -428,7 +446,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
                           a.key1, hc, bad);
           z = to_store<F>(z);
-          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, z, mu, E, fl, c.v);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, z, mu, E, fl, c.v, wfx);
           lc[J].dep += 1;
         } else {
           z = to_store<F>(z);
@@ -456,6 +474,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           Q.hi[p] = hi;
           Q.E[p] = E2;
           Q.fl[p] = (flmid & (kLayerMask << kLayerShift)) | (gen << kGenShift);
+          Q.w[p] = wfx;  // a secondary carries its parent's weight
         }
         qn += __popcll(mq);
       }
@@ -478,6 +497,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
             at(sp.E, pos) = E;
             at(sp.uid, pos) = (uint64_t)lo | ((uint64_t)hi << 32);
             at(sp.fl, pos) = fl;
+            if (WT) at(sp.w, pos) = wfx;
             if (DEBUG) at(sp.ev, pos) = evp;
           } else {
             atomicOr(a.status, kStOverflow);
@@ -511,6 +531,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       const int idx = act ? lane : 0;
       double cz = Q.z[idx];
       const uint32_t lo = Q.lo[idx], phi = Q.hi[idx], cE = Q.E[idx], pfl = Q.fl[idx];
+      const uint32_t cw = WT ? Q.w[idx] : kW1;
       wave_sync();
       double cmu = 0.0;
       uint32_t cfl = kDead, lin = 0, pos = 0;
@@ -531,7 +552,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0,
                         a.key1, h, bad);
         cz = to_store<F>(cz);
-        deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, cz, cmu, cE, cfl, cc.v);
+        deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, cz, cmu, cE, cfl, cc.v, cw);
         lc[J].dep += 1;
         lc[J].tr += h.tr;
         lc[J].ri += h.ri;
@@ -549,18 +570,19 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           at(sp.E, pos) = cE;
           at(sp.uid, pos) = (uint64_t)lo | ((uint64_t)lin << 32);
           at(sp.fl, pos) = cfl;
+          if (WT) at(sp.w, pos) = cw;
           if (DEBUG) at(sp.ev, pos) = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
         } else {
           atomicOr(a.status, kStOverflow);
         }
       }
-      if constexpr (J + 1 < T) cont(Sub<J + 1>{}, placed, pos, cz, cmu, cE, cfl, lo, lin);
+      if constexpr (J + 1 < T) cont(Sub<J + 1>{}, placed, pos, cz, cmu, cE, cfl, lo, lin, cw);
     };
 
     // re-read the top n slots of a sub-step's queue and bring z to the start of that step
     auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, uint32_t& g, double& z,
                          double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo, uint32_t& hi,
-                         uint64_t& evp) __attribute__((always_inline)) -> bool {
+                         uint64_t& evp, uint32_t& wfx) __attribute__((always_inline)) -> bool {
       wave_sync();
       const bool act = lane < n;
       g = act ? SQ[sn - n + lane] : 0u;
@@ -576,6 +598,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
         if (DEBUG) evp = at(sp.ev, g);
+        wfx = WT ? at(sp.w, g) : kW1;
         const int d = phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
           const double v = ET ? speed_at(I, et, layer_of(fl), (int)(fl & kSpinMask), E)
@@ -588,25 +611,26 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // ---- the last sub-step of the launch through the general path, for the top n slots
     // of its queue
     auto drain_last = [&](int n) __attribute__((always_inline)) {
-      uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0;
+      uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
       double z = 0.0, mu = 0.0;
       uint64_t evp = 0;
       const bool act = pop_state(T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
-                                 a.sub_z_phase[T - 1], g, z, mu, E, fl, lo, hi, evp);
-      general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, slot);
+                                 a.sub_z_phase[T - 1], g, z, mu, E, fl, lo, hi, evp, wfx);
+      general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
       drain_kids(Sub<T - 1>{});
     };
     // ---- sub-step 0 of a two-step launch through the general path for the top n slots
     // of its queue; survivors and newborns continue with sub-step 1
     auto drain_first = [&](int n) __attribute__((always_inline)) {
       if constexpr (T > 1) {
-        uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0;
+        uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
         double z = 0.0, mu = 0.0;
         uint64_t evp = 0;
         const bool act =
-            pop_state(SQ0, sn0, n, a.sub_z_phase[0], g, z, mu, E, fl, lo, hi, evp);
-        const bool surv = general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, slot);
-        cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi);
+            pop_state(SQ0, sn0, n, a.sub_z_phase[0], g, z, mu, E, fl, lo, hi, evp, wfx);
+        const bool surv =
+            general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
+        cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi, wfx);
         drain_kids(Sub<0>{});
       }
     };
@@ -642,6 +666,13 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           if (I.lay[q].x <= z) l = q;
         const uint32_t fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift) |
                             ((uint32_t)a.sub_z_phase[J] << kStampShift);
+        if (WT) {
+          // weight of the primary (Eq. 10), from the weight rows behind the energy tables
+          const uint32_t wfx = primary_weight(
+              I, a.etab + I.etab_off + 2 * (int)I.n_ch * I.e_nodes, (int)s, E);
+          if ((int)pos < cap) at(sp.w, pos) = wfx;
+          atomicAdd(&s_cnt[J][PIC_C_W_INJECTED], (unsigned long long)wfx);
+        }
         if ((int)pos < cap) {
           placed = true;
           at(sp.z, pos) = (F)z;
@@ -661,7 +692,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // unconditionally (a dead slot's fields are loaded too), so that no load waits on
     // another and each wave keeps two carriers' worth of loads in flight.
     F nz = 0, nmu = 0;
-    uint32_t nE = 0, nfl = kDead;
+    uint32_t nE = 0, nfl = kDead, nw = kW1;
     uint64_t nu = 0;
     auto fetch = [&](int t) __attribute__((always_inline)) {
       if (t < tail0) {
@@ -671,6 +702,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nmu = at(sp.mu, g);
         nE = at(sp.E, g);
         nu = at(sp.uid, g);
+        if (WT) nw = at(sp.w, g);
       } else {
         nfl = kDead;
       }
@@ -685,7 +717,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       if (streaming) {
         const int t = tb + lane;
         const F rz = nz, rmu = nmu;
-        const uint32_t rE = nE, rfl = nfl;
+        const uint32_t rE = nE, rfl = nfl, rw = nw;
         const uint64_t ru = nu;
         fetch(t + (int)blockDim.x);
         const bool have = t < total;
@@ -706,7 +738,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           const double x = a.dt * (inel_rate<ET>(c, tau2, rE) + I.lay[l].z);
           // u01(w) < x  <=>  w + 0.5 < x 2^32  <=>  w < x 2^32 - 0.5 (both sides exact)
           const double thr = x * 0x1p32 - 0.5;
-          const long long cv = cur_fixed(c.v, mu);
+          const long long cv = cur_val<MODE>(a, c.v, mu, rw);
           // energy bin once for both sub-steps (E does not change on the common path)
           const int eb = (a.sub_dens_on[0] || a.sub_dens_on[T - 1]) ? ebin(a, s_edges, s_ebkt, rE) : 0;
 #pragma unroll
@@ -722,9 +754,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                 left_at = j;
               } else {
                 z = to_store<F>(ze);
-                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, z, eb, rfl, cv);
+                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, z, eb, rfl, cv, rw);
                 if constexpr (T > 1)
-                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, z, eb, rfl, cv);
+                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, z, eb, rfl, cv, rw);
                 lc[j].dep += 1;
                 n_fast[j] += 1;
               }
@@ -809,6 +841,7 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
     F z = 0, mu = 0;
     uint32_t E = 0;
     uint64_t u = 0, ev = 0;
+    uint32_t wv = 0;
     double row[kMaxCausalK];
     double rr = 0.0;
     if (keep) {
@@ -817,6 +850,7 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
       E = a.E[base + t];
       u = a.uid[base + t];
       if (a.ev) ev = a.ev[base + t];
+      if (a.w) wv = a.w[base + t];
       if (a.S) {
 #pragma unroll
         for (int k = 0; k < kMaxCausalK; ++k)
@@ -841,6 +875,7 @@ __global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
       a.uid[d] = u;
       a.flags[d] = fl;
       if (a.ev) a.ev[d] = ev;
+      if (a.w) a.w[d] = wv;
       if (a.S) {
 #pragma unroll
         for (int k = 0; k < kMaxCausalK; ++k)
@@ -864,11 +899,11 @@ __global__ void k_fill32(uint32_t* p, int64_t n, uint32_t v) {
 }
 
 __global__ void k_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
-                          double* dout, double* cout) {
+                          double* dout, double* cout, double dscale) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd || i < nc;
        i += stride) {
-    if (dout && i < nd) dout[i] = (double)dens[i];
+    if (dout && i < nd) dout[i] = (double)dens[i] * dscale;
     if (cout && i < nc) cout[i] = (double)cur[i] * 0x1p-32;
   }
 }
@@ -887,10 +922,10 @@ static hipError_t launch_prec(const StepArgs& a, int mode, const StepLaunch& L, 
     case kModeDebug: launch_mode<F, T, kModeDebug>(a, L, s); break;
     case kModeDensGlobal: launch_mode<F, T, kModeDensGlobal>(a, L, s); break;
     case kDG: launch_mode<F, T, kDG>(a, L, s); break;
-    case kModeETab: launch_mode<F, T, kModeETab>(a, L, s); break;
-    case kModeETab | kModeDebug: launch_mode<F, T, kModeETab | kModeDebug>(a, L, s); break;
-    case kModeETab | kModeDensGlobal: launch_mode<F, T, kModeETab | kModeDensGlobal>(a, L, s); break;
-    case kModeETab | kDG: launch_mode<F, T, kModeETab | kDG>(a, L, s); break;
+    case kModeExt: launch_mode<F, T, kModeExt>(a, L, s); break;
+    case kModeExt | kModeDebug: launch_mode<F, T, kModeExt | kModeDebug>(a, L, s); break;
+    case kModeExt | kModeDensGlobal: launch_mode<F, T, kModeExt | kModeDensGlobal>(a, L, s); break;
+    case kModeExt | kDG: launch_mode<F, T, kModeExt | kDG>(a, L, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -910,10 +945,10 @@ static hipError_t raise_lds(size_t bytes) {
                         reinterpret_cast<const void*>(&k_step<F, T, kModeDebug>),
                         reinterpret_cast<const void*>(&k_step<F, T, kModeDensGlobal>),
                         reinterpret_cast<const void*>(&k_step<F, T, kDG>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kModeDebug>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kModeDensGlobal>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeETab | kDG>)})
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kModeDebug>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kModeDensGlobal>),
+                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kDG>)})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
 }
@@ -929,7 +964,7 @@ hipError_t set_step_lds_limit(size_t bytes) {
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
   const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
-                   (a.etab ? kModeETab : 0);
+                   (a.etab || a.wt ? kModeExt : 0);
   if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
   hipError_t e;
   if (a.n_sub == 2)
@@ -958,13 +993,13 @@ hipError_t launch_fill32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 }
 
 hipError_t launch_convert(const uint64_t* dens, int64_t nd, const int64_t* cur, int64_t nc,
-                          double* dout, double* cout, hipStream_t s) {
+                          double* dout, double* cout, double dscale, hipStream_t s) {
   const int64_t n = nd > nc ? nd : nc;
   if (n <= 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, s, dens, nd, cur, nc,
-                     dout, cout);
+                     dout, cout, dscale);
   return hipGetLastError();
 }
 

@@ -7,6 +7,9 @@ All functions take the per-instance bins as returned by `PicSim.deposit()` /
 * current  cur[slot, z, spin]      sum of v cos(theta) per cell, nm/fs (Eq. 23 moment),
 * gen      gen[slot, z, spin]      sum of generation labels per density cell.
 
+With weighted superparticles (Eq. 10) every moment is a sum of weights, and
+`normalization` gives the constant C that scales them to the excitation density.
+
 Time slot n holds the moments after n+1 steps (t = (n+1) dt, times the stride).
 """
 from __future__ import annotations
@@ -21,6 +24,16 @@ def _np(a) -> np.ndarray:
     if hasattr(a, "detach"):
         a = a.detach().cpu().numpy()
     return np.asarray(a, dtype=np.float64)
+
+
+def normalization(counters, rho_exc: float) -> float:
+    """The constant C of Eq. (10), rho_exc / sum_i w_i, taken over the primaries (the
+    excitation that rho_exc describes): the injected-weight counter holds sum w in 2^-16
+    units.  Multiplying a (weighted) density or current moment by C turns it into a
+    density of the excitation rho_exc.  `counters` is one instance's [n_steps, NC] array
+    (a batch of instances shares the counters, so use it with a single instance)."""
+    w = float(np.asarray(counters)[:, 11].sum()) * 2.0 ** -16
+    return rho_exc / w if w > 0 else 0.0
 
 
 def hot_density(dens) -> np.ndarray:

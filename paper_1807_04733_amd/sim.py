@@ -61,6 +61,14 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
                 for k in range(n):
                     s.v_node[c][k] = float(v_tab[c, k])
                     s.r_node[c][k] = float(it.r_tab[c, k])
+        w_tab = getattr(it, "w_tab", None)
+        if w_tab is not None:
+            # superparticle weights per (spin, node)
+            s.w_nodes = int(w_tab.shape[1])
+            s.w_scale = float(it.w_scale)
+            for sp in range(2):
+                for k in range(s.w_nodes):
+                    s.w_node[sp][k] = float(w_tab[sp, k])
     cfg = _abi.PicConfig()
     cfg.n_instances = len(problem.instances)
     cfg.inst = insts
@@ -80,6 +88,8 @@ def make_config(problem, *, debug: bool = False, slab_primaries: int = 0,
         flags |= _abi.F_GEN_MOMENT
     if getattr(problem, "absorb_next", False):
         flags |= _abi.F_ABSORB_NEXT
+    if getattr(problem, "weighted", False):
+        flags |= _abi.F_WEIGHTS
     cfg.flags = flags
     if problem.n_ebins > _abi.MAX_EBINS:
         raise ValueError("too many energy bins")
@@ -335,6 +345,8 @@ class PicSim:
                    gen=((fl >> np.uint32(lay.flags_gen_shift)) & np.uint32(0xFF)).astype(np.int32),
                    dead=((fl & np.uint32(lay.flags_dead_bit)) != 0),
                    inst=inst[slab_of].astype(np.int32))
+        if lay.off_w >= 0:
+            out["w"] = arr(lay.off_w, cap, torch.int32)[ti].cpu().numpy().view(np.uint32)
         if lay.off_ev >= 0:
             ev = arr(lay.off_ev, cap, torch.int64)[ti].cpu().numpy().view(np.uint64)
             out["ev"] = np.stack([(ev >> np.uint64(16 * k)) & np.uint64(0xFFFF)

@@ -40,6 +40,8 @@ def compare_records(dev: dict, ref: dict, fp64: bool, z_tol: float = 0.0):
     same &= dev["dead"][ia] == (ref["dead"][ib] >= 0)
     if "ev" in dev:
         same &= np.all(dev["ev"][ia] == ref["ev"][ib], axis=1)
+    if "w" in dev:
+        same &= dev["w"][ia] == ref["w"][ib]
     return dict(joined=len(ia), n_dev=na, n_ref=nb, match=int(same.sum()),
                 frac=float(same.mean()) if len(ia) else 1.0, bad=np.where(~same)[0][:10],
                 ia=ia, ib=ib)

@@ -92,6 +92,18 @@ def test_gradient_matches_oracle_energy_dependent_channels(torch_gpu, oracle_mod
     assert np.abs(g - ref).max() <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_gradient_matches_oracle_weighted(torch_gpu, oracle_mod, estimator):
+    """Weighted superparticles: every deposit term is scaled by the carrier's weight."""
+    prob = W.variant(W.config3(n_primaries=5000, n_steps=90), weights=True)
+    gd, gc = _random_g(prob, 5)
+    g = _gpu_grad(prob, gd, gc, estimator, slab_primaries=1000, capacity_factor=30)
+    ref = oracle_mod.run(prob, g_dens=gd, g_cur=gc, grad_per_tree=bool(estimator)).grad
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(g - ref).max() <= 1e-9 * scale
+
+
 def test_gradient_matches_oracle_batched_tables(torch_gpu, oracle_mod):
     prob = W.config4(n_instances=2, primaries_per_instance=800, n_steps=300)
     gd, gc = _random_g(prob, 2, frac=0.02)

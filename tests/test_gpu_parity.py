@@ -61,14 +61,18 @@ def assert_parity(dev, ref, prob, *, exact_bins=True):
              f"match {r['frac']:.6f}")
         assert r["joined"] >= 0.999 * r["n_ref"]
         assert r["frac"] >= 0.9999, r["bad"]
+    # weighted runs: integer density / generation bins in 2^-16 units of weight
+    ds = 2.0 ** -16 if prob.weighted else 1.0
+    if dev["parts"] is not None and prob.weighted:
+        assert "w" in dev["parts"]
     for i in range(len(prob.instances)):
-        assert rel_l1(dev["fd"][i], ref.dens[i]) <= 1e-5
+        assert rel_l1(dev["fd"][i], ref.dens[i] * ds) <= 1e-5
         assert rel_l1(dev["fc"][i], ref.cur_float(i)) <= 1e-5
         if exact_bins:
             assert np.array_equal(dev["dens"][i], ref.dens[i])
             assert np.array_equal(dev["cur"][i], ref.cur[i])
         if dev["gen"] is not None:
-            assert np.array_equal(dev["gen"][i], ref.gen[i].astype(np.float64))
+            assert np.array_equal(dev["gen"][i], ref.gen[i].astype(np.float64) * ds)
     if exact_bins:
         assert np.array_equal(dev["cnt"], ref.counters)
 
@@ -133,7 +137,9 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
                    {"block": 512, "grid": 300, "compact_every": 3, "z_every": 5,
                     "sub_steps": 2},
                    {"block": 256, "grid": 2000, "compact_every": 2, "z_every": 2,
-                    "sub_steps": 2, "use_graph": 0}):
+                    "sub_steps": 2, "use_graph": 0},
+                   {"block": 1024, "grid": 5, "compact_every": 4, "z_every": 4,
+                    "sub_steps": 2}):
         from paper_1807_04733_amd import PicSim
         _say(f"[parity] launch shape {tuning}")
         sim = PicSim(prob, slab_primaries=1000, tuning=tuning)
@@ -197,6 +203,32 @@ def test_energy_tables_mixed_batch(torch_gpu, oracle_mod):
     prob.instances[1].v_tab = prob.instances[1].r_tab = None
     prob.e_min_fx = W.e_fx(0.3)
     dev, ref = run_both(prob, oracle_mod, slab_primaries=400, tuning={"sub_steps": 2})
+    assert_parity(dev, ref, prob)
+
+
+@pytest.mark.parametrize("sub_steps", [1, 2])
+def test_weighted_superparticles(torch_gpu, oracle_mod, sub_steps):
+    """Weighted superparticles (Eq. 10) from importance sampling of the source: weights
+    per record, weighted density / current / generation bins and the injected-weight
+    counter equal the oracle's, in one- and two-step launches."""
+    prob = W.variant(W.config1(parallel=False, n_primaries=4000, n_steps=150),
+                     weights=True, gen_moment=True)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=900,
+                        tuning={"sub_steps": sub_steps, "z_every": 4})
+    assert_parity(dev, ref, prob)
+    w = ref.records["w"]
+    assert w.min() != w.max()                      # the weights really differ
+
+
+def test_weights_with_energy_tables_batched(torch_gpu, oracle_mod):
+    """Weights together with energy-dependent channels and transmission, removal at the
+    next event, over a batch where one instance has no weight table (weight 1)."""
+    prob = W.variant(W.config4(n_instances=3, primaries_per_instance=1000, n_steps=240),
+                     energy_tables=True, weights=True, absorb_next=True, gen_moment=True)
+    prob.instances[2].w_tab = None
+    prob.e_min_fx = W.e_fx(0.3)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=400,
+                        tuning={"sub_steps": 2, "block": 1024, "grid": 3})
     assert_parity(dev, ref, prob)
 
 

@@ -92,3 +92,16 @@ def test_msd_and_alpha_from_bins(oracle_lib):
     assert np.max(np.abs(a[sel][:-1] - c[sel][:-1])) < 0.02
     assert abs(O.alpha_ballistic_diffusive(np.array([1e-3]), tau)[0] - 2.0) < 1e-3
     assert abs(O.alpha_ballistic_diffusive(np.array([1e5]), tau)[0] - 1.0) < 1e-3
+
+
+def test_normalization_constant(oracle_lib):
+    """C of Eq. (10) is rho_exc over the summed primary weights: the number of primaries
+    without weights, the sum of the primaries' record weights with them."""
+    prob = W.config1(parallel=False, n_primaries=1500, n_steps=30)
+    res = oracle_lib.run(prob)
+    assert O.normalization(res.counters, 3.0) == 3.0 / 1500
+    wp = W.variant(prob, weights=True)
+    res = oracle_lib.run(wp, records=True)
+    prim = (res.records["uid"] >> np.uint64(32)) == 0
+    wsum = res.records["w"][prim].astype(np.float64).sum() * 2.0 ** -16
+    assert abs(O.normalization(res.counters, 3.0) * wsum / 3.0 - 1.0) < 1e-15

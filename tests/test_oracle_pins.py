@@ -527,3 +527,88 @@ def test_injection_distributions(oracle_lib):
     assert abs(E.mean() - 1.25) < 4 * E.std() / math.sqrt(len(E))
     mu = rec["mu"]
     assert abs(mu.mean()) < 4 * mu.std() / math.sqrt(len(mu))
+
+
+# --------------------------------------------------------------------------- weights (Eq. 10)
+def _weighted(prob, w_tab, w_scale, q_up=None):
+    insts = [replace(it, w_tab=np.asarray(w_tab, np.float64), w_scale=w_scale,
+                     src_up_frac=it.src_up_frac if q_up is None else q_up)
+             for it in prob.instances]
+    return replace(prob, instances=insts, weighted=True)
+
+
+def test_unit_weights_reduce_to_counts(oracle_lib):
+    """Weight 1 for every superparticle: the weighted density and generation moment are
+    the counts times 2^16 and the current is the unweighted current, bin by bin; the
+    injected weight is 2^16 per primary."""
+    prob = W.config1(parallel=False, n_primaries=3000, n_steps=80)
+    prob.gen_moment = True
+    ref = _run(oracle_lib, prob)
+    res = _run(oracle_lib, _weighted(prob, np.ones((2, 1)), 0.0))
+    assert np.array_equal(res.dens[0], ref.dens[0] * np.uint64(65536))
+    assert np.array_equal(res.gen[0], ref.gen[0] * np.uint64(65536))
+    assert np.array_equal(res.cur[0], ref.cur[0])
+    assert np.array_equal(res.counters, ref.counters)
+    assert np.array_equal(res.counters[:, 11], 65536 * res.counters[:, 0])
+
+
+def test_weights_follow_the_table_and_are_inherited(oracle_lib):
+    """A primary's weight is the linear interpolation of its spin's row at its initial
+    energy (checked with numpy's interp, to one unit of 2^-16 for the different rounding
+    order), every secondary carries its root's weight, the injected-weight counter is the
+    sum over primaries, and the density moment sums the weights of the carriers it
+    counts."""
+    prob = W.config1(parallel=True, n_primaries=2000, n_steps=40)
+    nodes, e_max = 9, 2.0
+    e = np.arange(nodes) * (e_max / (nodes - 1))
+    w_tab = np.stack([0.5 + 0.7 * e, 2.0 - 0.6 * e])
+    wp = _weighted(prob, w_tab, (nodes - 1) / e_max)
+    res = _run(oracle_lib, wp, records=True)
+    rec = res.records
+    prim = _primaries(rec)
+    # primaries frozen at injection: rerun with no motion and no scattering
+    frozen = replace(wp, n_steps=1, instances=[replace(wp.instances[0], v=np.zeros(4),
+                                                       inv_tau0=np.zeros(4))])
+    f = _run(oracle_lib, frozen, records=True).records
+    fp = _primaries(f)
+    E0, s0, w0 = f["E"][fp] / W.E_ONE, f["spin"][fp], f["w"][fp].astype(np.int64)
+    want = np.where(s0 == 0, np.interp(E0, e, w_tab[0]), np.interp(E0, e, w_tab[1]))
+    assert np.abs(w0 - np.rint(want * 65536)).max() <= 1
+    # inheritance: all carriers of a tree carry the root's weight
+    root = (rec["uid"] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    wroot = np.zeros(root.max() + 1, np.int64)
+    wroot[root[prim]] = rec["w"][prim]
+    assert np.array_equal(rec["w"].astype(np.int64), wroot[root])
+    assert res.counters[:, 11].sum() == rec["w"][prim].astype(np.int64).sum()
+    # the last density slot sums the weights of the carriers alive at the end
+    alive = rec["dead"] < 0
+    last = (prob.n_steps - 1) // prob.dens_stride
+    if (prob.n_steps - 1) % prob.dens_stride == 0:
+        assert res.dens[0][last].sum() == rec["w"][alive].astype(np.int64).sum()
+
+
+def test_spin_importance_sampling_is_unbiased(oracle_lib):
+    """Spin sampled 50/50 with weights p/q and (1-p)/(1-q) (p = 0.6): the weighted
+    hot-carrier density per spin and the spin current agree with the unbiased unweighted
+    simulation in expectation (8 seeds each, 4 standard errors of the difference), and the
+    total injected weight matches the number of primaries."""
+    p, q = W.SPIN_UP_FRAC, 0.5
+    stats = {"plain": [], "weighted": []}
+    for seed in range(8):
+        prob = W.config1(parallel=False, n_primaries=3000, n_steps=60, seed=seed)
+        plain = _run(oracle_lib, prob)
+        wt = np.array([[p / q], [(1 - p) / (1 - q)]])
+        wres = _run(oracle_lib, _weighted(replace(prob, seed=100 + seed), wt, 0.0, q_up=q))
+        for name, r, scale in (("plain", plain, 1.0), ("weighted", wres, 2.0 ** -16)):
+            d = r.dens[0][-1].astype(np.float64) * scale
+            per_spin = d.sum(axis=(0, 1))
+            js = r.cur_float(0)[-1].sum(axis=0)
+            stats[name].append(np.concatenate([per_spin, js[:1] - js[1:]]))
+        # E[w] = 1 and var(w) = 0.5 * 0.2^2 + 0.5 * 0.2^2 = 0.04 per primary
+        assert abs(wres.counters[:, 11].sum() / 65536 - 3000) < 4 * math.sqrt(3000 * 0.04)
+    a, b = np.array(stats["plain"]), np.array(stats["weighted"])
+    diff = a.mean(0) - b.mean(0)
+    se = np.sqrt(a.var(0, ddof=1) / len(a) + b.var(0, ddof=1) / len(b))
+    assert np.all(np.abs(diff) < 4 * se + 1e-9), (diff, se)
+    # the sampling really differs: the unweighted count of spin-up carriers moves with q
+    assert b[:, 0].mean() != a[:, 0].mean()

@@ -99,6 +99,11 @@ class Instance:
     v_tab: Optional[np.ndarray] = None
     r_tab: Optional[np.ndarray] = None
     e_scale: float = 0.0
+    # optional superparticle weights (Eq. 10): a primary of spin s and initial energy E0
+    # carries the weight interpolated from w_tab[s, k] at E = k / w_scale eV (clamped);
+    # None = weight 1.  Used when Problem.weighted is set.
+    w_tab: Optional[np.ndarray] = None
+    w_scale: float = 0.0
 
     @property
     def e_nodes(self) -> int:
@@ -141,6 +146,7 @@ class Problem:
     name: str = ""
     gen_moment: bool = False      # also bin the generation label (with the density)
     absorb_next: bool = False     # below E_min: removed at the next event, not at once
+    weighted: bool = False        # moments are weighted sums (Eq. 10)
 
     @property
     def n_ebins(self) -> int:
@@ -320,13 +326,33 @@ def synthetic_channel_tables(v: Sequence[float], nodes: int = 64, e_max: float =
     return v_tab, r_tab, (nodes - 1) / e_max
 
 
+def importance_weights(inst: Instance, q_up: float = 0.5, nodes: int = 16,
+                       e_max: float = 2.0, slope: float = 1.0):
+    """Source importance sampling (Eq. 10 weights): the spin is sampled with probability
+    q_up instead of the instance's src_up_frac p, and the energy uniformly in the pump
+    window while the physical spectrum is taken proportional to 1 + slope * E / 1 eV over
+    that window.  The weight of a primary is the ratio of physical to sampling density:
+    (p / q_up or (1 - p) / (1 - q_up)) * (1 + slope E) / mean(1 + slope E).  Returns
+    (src_up_frac to sample with, w_tab (2, nodes), w_scale)."""
+    p = inst.src_up_frac
+    e = np.arange(nodes) * (e_max / (nodes - 1))
+    rows = []
+    for s, ws in ((0, p / q_up), (1, (1.0 - p) / (1.0 - q_up))):
+        lo = inst.src_e_lo[s] * 2.0 ** -30
+        hi = (int(inst.src_e_lo[s]) + int(inst.src_e_span[s])) * 2.0 ** -30
+        rows.append(ws * (1.0 + slope * e) / (1.0 + slope * 0.5 * (lo + hi)))
+    return q_up, np.stack(rows).astype(np.float64), (nodes - 1) / e_max
+
+
 def variant(problem: Problem, *, tau_el: Optional[float] = None, transparent: bool = False,
             secondaries: Optional[bool] = None, absorb_next: Optional[bool] = None,
-            gen_moment: Optional[bool] = None, energy_tables: bool = False) -> Problem:
+            gen_moment: Optional[bool] = None, energy_tables: bool = False,
+            weights: bool = False) -> Problem:
     """A copy of `problem` with the physics switches of the paper's comparisons (Sec. V):
     an elastic channel of lifetime tau_el in every layer, transparent interfaces (T = 1),
-    secondaries on / off, removal at the next event, the generation moment, and
-    energy-dependent speeds and lifetimes (synthetic tables)."""
+    secondaries on / off, removal at the next event, the generation moment,
+    energy-dependent speeds and lifetimes (synthetic tables), and weighted superparticles
+    from importance sampling of the source (Eq. 10)."""
     insts = []
     for it in problem.instances:
         it = replace(it)
@@ -336,8 +362,12 @@ def variant(problem: Problem, *, tau_el: Optional[float] = None, transparent: bo
             it.T = np.ones_like(it.T)
         if energy_tables:
             it.v_tab, it.r_tab, it.e_scale = synthetic_channel_tables(it.v)
+        if weights:
+            it.src_up_frac, it.w_tab, it.w_scale = importance_weights(it)
         insts.append(it)
     out = replace(problem, instances=insts)
+    if weights:
+        out.weighted = True
     if secondaries is not None:
         out.secondaries = secondaries
     if absorb_next is not None:
