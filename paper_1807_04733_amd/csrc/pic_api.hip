@@ -788,8 +788,8 @@ pic_status pic_reset(pic_ctx* c) {
 pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (!c || !t) return fail(PIC_EINVAL, "null argument");
   const int b = t->block;
-  if (!(b == 64 || b == 128 || b == 256 || b == 512 || b == 1024))
-    return fail(PIC_EINVAL, "block must be 64, 128, 256, 512 or 1024");
+  if (!(b == 64 || b == 128 || b == 256 || b == 512))
+    return fail(PIC_EINVAL, "block must be 64, 128, 256 or 512");
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
   if (t->z_every < 1 || t->z_every > kMaxZEvery) return fail(PIC_EINVAL, "z_every must be 1..8");
@@ -981,7 +981,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   float best_ms = 1e30f;
   pic_tuning win = cur;
   // stage 1: workgroup size and persistent grid
-  for (int block : {128, 256, 512, 1024}) {
+  for (int block : {128, 256, 512}) {
     if (lds_for(c, block) > c->max_lds) continue;
     for (int grid : {256, 512, 1024, 2048}) {
       pic_tuning t = cur;

@@ -19,6 +19,8 @@
 // Histograms are privatised per workgroup in LDS and merged into the int64 bins with
 // global atomics only for non-zero entries.  All decisions use binary64 arithmetic in
 // the order written here; the file is built with -ffp-contract=off.
+#include <utility>
+
 #include "pic_device.h"
 
 #pragma clang fp contract(off)
@@ -28,8 +30,8 @@ namespace pic {
 // Compile-time launch modes of the step kernel.
 constexpr int kModeDebug = 1;       // keep per-particle event counts
 constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slice does not fit)
-constexpr int kModeExt = 8;         // energy-dependent speeds and rates (tables in LDS) and / or
-                                    // weighted superparticles (StepArgs::wt)
+constexpr int kModeTab = 8;         // energy-dependent speeds and rates (tables in LDS)
+constexpr int kModeWt = 16;         // weighted superparticles (StepArgs::wt)
 
 // Compile-time sub-step index for the generic lambdas of k_step.
 template <int V>
@@ -40,7 +42,7 @@ struct Sub {
 // weighted moments: the density and generation slices hold u64 sums of weights
 template <int MODE>
 __device__ __forceinline__ bool weighted(const StepArgs& a) {
-  return (MODE & kModeExt) && a.wt != nullptr;
+  return (MODE & kModeWt) != 0;
 }
 
 // Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
@@ -202,9 +204,9 @@ constexpr int kSlowQ1 = 256;
 // way.  New primaries (source term, Eq. 17) of a sub-step are appended with their initial
 // state and queued for its general path.
 template <typename F, int T, int MODE>
-__global__ void __launch_bounds__(1024, 4) k_step(StepArgs a) {
+__global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
-  constexpr bool ET = (MODE & kModeExt) != 0;
+  constexpr bool ET = (MODE & kModeTab) != 0;
   // dynamic LDS: [histogram slices of the sub-steps | energy tables | per wave: newborn
   // queue, slot queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -913,22 +915,20 @@ static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
   hipLaunchKernelGGL((k_step<F, T, MODE>), dim3(L.grid), dim3(L.block), L.lds, s, a);
 }
 
-constexpr int kDG = kModeDebug | kModeDensGlobal;
+// the launch modes that are instantiated: debug x density placement x tables x weights
+using StepModes = std::integer_sequence<int, 0, 1, 4, 5, 8, 9, 12, 13, 16, 17, 20, 21, 24, 25,
+                                        28, 29>;
+
+template <typename F, int T, int... Ms>
+static hipError_t launch_any(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s,
+                             std::integer_sequence<int, Ms...>) {
+  const bool found = ((mode == Ms ? (launch_mode<F, T, Ms>(a, L, s), true) : false) || ...);
+  return found ? hipGetLastError() : hipErrorInvalidValue;
+}
 
 template <typename F, int T>
 static hipError_t launch_prec(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s) {
-  switch (mode) {
-    case 0: launch_mode<F, T, 0>(a, L, s); break;
-    case kModeDebug: launch_mode<F, T, kModeDebug>(a, L, s); break;
-    case kModeDensGlobal: launch_mode<F, T, kModeDensGlobal>(a, L, s); break;
-    case kDG: launch_mode<F, T, kDG>(a, L, s); break;
-    case kModeExt: launch_mode<F, T, kModeExt>(a, L, s); break;
-    case kModeExt | kModeDebug: launch_mode<F, T, kModeExt | kModeDebug>(a, L, s); break;
-    case kModeExt | kModeDensGlobal: launch_mode<F, T, kModeExt | kModeDensGlobal>(a, L, s); break;
-    case kModeExt | kDG: launch_mode<F, T, kModeExt | kDG>(a, L, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return launch_any<F, T>(a, mode, L, s, StepModes{});
 }
 
 size_t step_static_lds() {
@@ -938,19 +938,17 @@ size_t step_static_lds() {
   return fa.sharedSizeBytes;
 }
 
-template <typename F, int T>
-static hipError_t raise_lds(size_t bytes) {
+template <typename F, int T, int... Ms>
+static hipError_t raise_lds_all(size_t bytes, std::integer_sequence<int, Ms...>) {
   hipError_t e = hipSuccess;
-  for (const void* f : {reinterpret_cast<const void*>(&k_step<F, T, 0>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeDebug>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeDensGlobal>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kDG>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kModeDebug>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kModeDensGlobal>),
-                        reinterpret_cast<const void*>(&k_step<F, T, kModeExt | kDG>)})
+  for (const void* f : {reinterpret_cast<const void*>(&k_step<F, T, Ms>)...})
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
+}
+
+template <typename F, int T>
+static hipError_t raise_lds(size_t bytes) {
+  return raise_lds_all<F, T>(bytes, StepModes{});
 }
 
 hipError_t set_step_lds_limit(size_t bytes) {
@@ -964,7 +962,7 @@ hipError_t set_step_lds_limit(size_t bytes) {
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
   const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
-                   (a.etab || a.wt ? kModeExt : 0);
+                   (a.etab_words > 0 ? kModeTab : 0) | (a.wt ? kModeWt : 0);
   if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
   hipError_t e;
   if (a.n_sub == 2)
