@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // unconditionally (a dead slot's fields are loaded too), so that no load waits on
     // another and each wave keeps two carriers' worth of loads in flight.
     F nz = 0, nmu = 0;
-    uint32_t nE = 0, nfl = kDead, nw = kW1;
+    uint32_t nE = 0, nfl = kDead;
     uint64_t nu = 0;
     auto fetch = [&](int t) __attribute__((always_inline)) {
       if (t < tail0) {
@@ -704,7 +704,6 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nmu = at(sp.mu, g);
         nE = at(sp.E, g);
         nu = at(sp.uid, g);
-        if (WT) nw = at(sp.w, g);
       } else {
         nfl = kDead;
       }
@@ -719,9 +718,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       if (streaming) {
         const int t = tb + lane;
         const F rz = nz, rmu = nmu;
-        const uint32_t rE = nE, rfl = nfl, rw = nw;
+        const uint32_t rE = nE, rfl = nfl;
         const uint64_t ru = nu;
         fetch(t + (int)blockDim.x);
+        // the weight is read for the current tile only (not prefetched): one register less
+        // held across the iteration
+        const uint32_t rw = WT && t < tail0 ? at(sp.w, (uint32_t)t) : kW1;
         const bool have = t < total;
         const bool from_soa = have && t < tail0;
         const bool is_new0 = have && !from_soa && t < tail0 + n_inj0;
