@@ -230,6 +230,27 @@ def test_weights_with_energy_tables_batched(torch_gpu, oracle_mod):
     assert_parity(dev, ref, prob)
 
 
+@pytest.mark.parametrize("kind", ["tables", "weights", "both"])
+def test_extended_modes_without_debug(torch_gpu, oracle_mod, kind):
+    """The production (non-debug) kernels of the table and weight modes, in two-step
+    launches with z write-back: bins, generation moment and counters equal the oracle's."""
+    prob = W.variant(W.config1(parallel=True, n_primaries=5000, n_steps=120),
+                     energy_tables=kind != "weights", weights=kind != "tables",
+                     gen_moment=True)
+    dev, ref = run_both(prob, oracle_mod, debug=False, records=False, slab_primaries=700,
+                        tuning={"sub_steps": 2, "z_every": 4, "compact_every": 3,
+                                "compact_frac": 0.0})
+    assert_parity(dev, ref, prob)
+
+
+def test_fp64_state_with_tables_and_weights(torch_gpu, oracle_mod):
+    """Binary64 particle state with energy tables and weights (records to 1e-9 nm)."""
+    prob = W.variant(W.config0(n_primaries=2500, n_steps=100), energy_tables=True,
+                     weights=True, gen_moment=True)
+    dev, ref = run_both(prob, oracle_mod, slab_primaries=600, tuning={"sub_steps": 2})
+    assert_parity(dev, ref, prob)
+
+
 def test_capacity_overflow_is_reported(torch_gpu):
     from paper_1807_04733_amd import PicSim, PicError
     prob = W.config0(n_primaries=2000, n_steps=100)
