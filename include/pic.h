@@ -147,7 +147,8 @@ typedef struct {
   int32_t  n_ebins;                         /* 1..PIC_MAX_EBINS */
   uint32_t e_edges[PIC_MAX_EBINS];          /* increasing lower edges (last bin open) */
   int32_t  dens_stride, cur_stride;         /* deposit every k-th step (slot n/k) */
-  int32_t  slab_primaries;                  /* primaries per slab; 0 = 4096 */
+  int32_t  slab_primaries;                  /* primaries per slab; 0 = 8192, or fewer
+                                               so that there are >= 2048 slabs */
   double   capacity_factor;                 /* slots per primary; 0 = floor(E0max/Emin)+2 */
   int32_t  adjoint;                         /* workspace for pic_backward: 0 none, 1 causal
                                                (K <= 16), 2 whole-tree, 3 both.  Needs equal
@@ -233,8 +234,9 @@ pic_status pic_generations(pic_ctx* ctx, double* gen_out);
  * device arrays laid out like pic_deposit's outputs (either may be NULL).  Parameter
  * order: ln tau0 of channels 0..n_channels-1, then T[t][e] row-major.  The result is an
  * unbiased Monte-Carlo estimate on the same random streams as the forward run.  The
- * replay does not compact, so the workspace must hold every carrier ever created
- * (capacity_factor).  Synchronizes. */
+ * replay advances one step per launch, writes z back every min(z_every, 4) steps and
+ * compacts every min(compact_every, 8) steps (compact_every 0: never), moving score rows
+ * (causal) and partial returns (whole-tree) with their carriers.  Synchronizes. */
 pic_status pic_backward(pic_ctx* ctx, const double* g_dens, const double* g_cur,
                         double* grad_out, int32_t estimator);
 

@@ -168,7 +168,13 @@ Plan make_plan(const pic_config* c) {
   Plan p;
   p.state_bytes = (c->flags & PIC_F_STATE_FP64) ? 8 : 4;
   p.debug = (c->flags & PIC_F_DEBUG) != 0;
-  const int P = c->slab_primaries > 0 ? c->slab_primaries : 4096;
+  // default slab size: 8192 primaries (fewer slab switches per workgroup), smaller when the
+  // problem would then give fewer than 2048 slabs (every workgroup of a launch needs work)
+  int64_t total = 0;
+  for (int i = 0; i < c->n_instances; ++i) total += c->inst[i].n_primaries;
+  const int P = c->slab_primaries > 0
+                    ? c->slab_primaries
+                    : (int)std::min<int64_t>(8192, std::max<int64_t>(256, (total + 2047) / 2048));
   p.n_dslots = (c->n_steps + c->dens_stride - 1) / c->dens_stride;
   p.n_cslots = (c->n_steps + c->cur_stride - 1) / c->cur_stride;
   for (int i = 0; i < c->n_instances; ++i) {
@@ -872,15 +878,18 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
   ca.S = adj == 1 ? A.S : nullptr;
   ca.K = adj == 1 ? p.K : 0;
   ca.r = adj == 2 ? A.r : nullptr;
-  const int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
+  // the replay advances one step per launch: z write-back at most every 4 steps and
+  // compaction at least every 8 (longer periods pay in the forward's two-step launches only)
+  const int K = std::max(1, std::min(c->tune.z_every, 4));
+  const int compact_every =
+      c->tune.compact_every > 0 ? std::min(c->tune.compact_every, 8) : 0;
   for (int n = 0; n < c->cfg.n_steps; ++n) {
     A.s = step_args(c, n);
     A.s.z_phase = n % K;
     A.s.z_write = (A.s.z_phase == K - 1 || n == c->cfg.n_steps - 1) ? 1 : 0;
     HIP_TRY(launch_adjoint(A, fp64, adj, grid, block, c->stream));
     // carriers move with their score rows (causal) or partial returns (tree pass 1)
-    if (c->tune.compact_every > 0 && (n + 1) % c->tune.compact_every == 0 &&
-        n + 1 < c->cfg.n_steps)
+    if (compact_every > 0 && (n + 1) % compact_every == 0 && n + 1 < c->cfg.n_steps)
       HIP_TRY(launch_compact(ca, fp64, 256, c->stream));
   }
   A.s = step_args(c, c->cfg.n_steps - 1);
