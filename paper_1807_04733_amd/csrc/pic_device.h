@@ -348,7 +348,4 @@ __device__ __forceinline__ uint64_t lanes_below() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Deposit one carrier at the end of the step: density per (depth, energy, spin) and the
-// fixed-point current v*cos(theta) per (depth, spin).
-
 }  // namespace pic

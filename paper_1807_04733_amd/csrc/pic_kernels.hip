@@ -7,10 +7,14 @@
 //   Transport(dt/2)  straight flight, vacuum reflection, stochastic interfaces (Eq. 18)
 //   Scattering(dt)   Monte-Carlo event with p = 1 - exp(-dt/tau_eff) (Eq. 2, Sec. III.A):
 //                    elastic (Eq. 8) or inelastic with an energy-conserving secondary
-//                    (Eqs. 6-7, 19); products below E_min are removed
+//                    (Eqs. 6-7, 19); products below E_min are removed (at once, or at
+//                    their next event)
 //   Transport(dt/2)  for the survivor and the newborn
-//   deposit          density and v*cos(theta) moments (Eqs. 16, 23) into LDS histograms
+//   deposit          density and v*cos(theta) moments (Eqs. 16, 23) into LDS histograms,
+//                    optionally the generation label and superparticle weights (Eq. 10)
 //
+// Speeds and inelastic rates are per-channel constants or energy tables (Fig. 1); each
+// option is a compile-time mode so that the plain kernel carries none of its code.
 // Data layout: structure-of-arrays particle state streamed once per launch (z,
 // cos(theta), energy, uid, flags), partitioned into slabs that each belong to one
 // instance.  A slab is processed by one workgroup per launch, which appends newborns
