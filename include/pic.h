@@ -172,7 +172,9 @@ typedef struct {
                              pass over its state; z_every is rounded up to a multiple */
 } pic_tuning;
 
-/* Where things live inside the workspace (byte offsets), for inspection and tests. */
+/* Where things live inside the workspace (byte offsets), for inspection and tests.
+ * The slab table lists each instance's slabs together, instances in decreasing order of
+ * primaries per slab times mean initial energy (the order in which slabs are processed). */
 typedef struct {
   int64_t n_slabs;
   int64_t capacity;       /* total particle slots */

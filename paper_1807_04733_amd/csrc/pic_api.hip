@@ -177,7 +177,27 @@ Plan make_plan(const pic_config* c) {
                     : (int)std::min<int64_t>(8192, std::max<int64_t>(256, (total + 2047) / 2048));
   p.n_dslots = (c->n_steps + c->dens_stride - 1) / c->dens_stride;
   p.n_cslots = (c->n_steps + c->cur_stride - 1) / c->cur_stride;
+  // Slabs are handed out in the order of the slab table, so the instances are laid out
+  // by decreasing expected work per slab (primaries per slab times the mean pump energy,
+  // to which the size of a cascade is proportional): the last slabs of a launch are then
+  // the lightest and the workgroups run out of work at nearly the same time.  Each
+  // instance's slabs stay contiguous, and no result depends on this order.
+  std::vector<int> order(c->n_instances);
+  std::vector<double> work(c->n_instances);
   for (int i = 0; i < c->n_instances; ++i) {
+    const pic_instance& I = c->inst[i];
+    const int64_t S = std::max<int64_t>(1, (I.n_primaries + P - 1) / P);
+    const double per = (double)((I.n_primaries + S - 1) / S);
+    const double up = std::min(1.0, std::max(0.0, I.src_up_frac));
+    const double e0 = up * ((double)I.src_e_lo[0] + 0.5 * I.src_e_span[0]) +
+                      (1.0 - up) * ((double)I.src_e_lo[1] + 0.5 * I.src_e_span[1]);
+    order[i] = i;
+    work[i] = per * e0;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+  p.n_slabs_of.assign(c->n_instances, 0);
+  p.slab0_of.assign(c->n_instances, 0);
+  for (const int i : order) {
     const pic_instance& I = c->inst[i];
     const int64_t N = I.n_primaries;
     const int64_t S = std::max<int64_t>(1, (N + P - 1) / P);
@@ -186,8 +206,8 @@ Plan make_plan(const pic_config* c) {
     int64_t cap = (int64_t)std::ceil((double)per * f) + 64;
     cap = (cap + 63) & ~int64_t(63);
     if (cap > (int64_t)1 << 28) cap = (int64_t)1 << 28;  // 32-bit byte offsets inside a slab
-    p.n_slabs_of.push_back((int32_t)S);
-    p.slab0_of.push_back((int32_t)p.slab_inst.size());
+    p.n_slabs_of[i] = (int32_t)S;
+    p.slab0_of[i] = (int32_t)p.slab_inst.size();
     for (int64_t k = 0; k < S; ++k) {
       p.slab_inst.push_back(i);
       p.slab_k.push_back((int32_t)k);
@@ -195,6 +215,9 @@ Plan make_plan(const pic_config* c) {
       p.slab_base.push_back(p.capacity);
       p.capacity += cap;
     }
+  }
+  for (int i = 0; i < c->n_instances; ++i) {
+    const pic_instance& I = c->inst[i];
     p.dens_off.push_back(p.dens_len);
     p.cur_off.push_back(p.cur_len);
     p.gen_off.push_back(p.gen_len);

@@ -106,6 +106,33 @@ def test_batched_instances(torch_gpu, oracle_mod):
     assert_parity(dev, ref, prob)
 
 
+def test_slab_table_in_work_order(torch_gpu):
+    # slabs are handed out in table order: instances by decreasing primaries per slab times
+    # mean pump energy, each instance's slabs contiguous and in order
+    import torch
+    from paper_1807_04733_amd import PicSim
+    prob = W.config2(n_instances=12, n_steps=4, prim_lo=50, prim_hi=5000)
+    P = 700
+    sim = PicSim(prob, slab_primaries=P)
+    lay = sim.layout
+    ns = lay.n_slabs
+    inst = sim.ws[lay.off_slab_inst:lay.off_slab_inst + 4 * ns].view(torch.int32).cpu().numpy()
+    sim.close()
+
+    def work(it):
+        S = max(1, -(-it.n_primaries // P))
+        per = -(-it.n_primaries // S)
+        up = it.src_up_frac
+        e0 = [float(it.src_e_lo[s]) + 0.5 * float(it.src_e_span[s]) for s in (0, 1)]
+        return per * (up * e0[0] + (1.0 - up) * e0[1])
+
+    runs = [int(inst[0])] + [int(b) for a, b in zip(inst[:-1], inst[1:]) if a != b]
+    assert sorted(runs) == list(range(len(prob.instances)))     # each instance contiguous
+    w = [work(prob.instances[i]) for i in runs]
+    assert all(x >= y for x, y in zip(w[:-1], w[1:]))
+    assert runs != sorted(runs)         # the workload's instances are not already in order
+
+
 def test_energy_tables_and_gaussian_pump(torch_gpu, oracle_mod):
     prob = W.config4(n_instances=3, primaries_per_instance=1500, n_steps=400)
     dev, ref = run_both(prob, oracle_mod, slab_primaries=400)
