@@ -168,13 +168,14 @@ Plan make_plan(const pic_config* c) {
   Plan p;
   p.state_bytes = (c->flags & PIC_F_STATE_FP64) ? 8 : 4;
   p.debug = (c->flags & PIC_F_DEBUG) != 0;
-  // default slab size: 8192 primaries (fewer slab switches per workgroup), smaller when the
-  // problem would then give fewer than 2048 slabs (every workgroup of a launch needs work)
+  // default slab size: 16384 primaries (fewer slab and instance switches per workgroup),
+  // smaller when the problem would then give fewer than 2048 slabs (every workgroup of a
+  // launch needs work)
   int64_t total = 0;
   for (int i = 0; i < c->n_instances; ++i) total += c->inst[i].n_primaries;
   const int P = c->slab_primaries > 0
                     ? c->slab_primaries
-                    : (int)std::min<int64_t>(8192, std::max<int64_t>(256, (total + 2047) / 2048));
+                    : (int)std::min<int64_t>(16384, std::max<int64_t>(256, (total + 2047) / 2048));
   p.n_dslots = (c->n_steps + c->dens_stride - 1) / c->dens_stride;
   p.n_cslots = (c->n_steps + c->cur_stride - 1) / c->cur_stride;
   // Slabs are handed out in the order of the slab table, so the instances are laid out
