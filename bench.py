@@ -172,6 +172,7 @@ def adjoint_leg(n_primaries: int, tune_steps: int):
     grad = sim.backward(None, g_cur, 0)
     t_bwd = time.perf_counter() - t0
     ps = particle_steps(cnt)
+    tuning = sim.tuning()
     sim.close()
     del d, c, g_cur
     torch.cuda.empty_cache()
@@ -181,7 +182,7 @@ def adjoint_leg(n_primaries: int, tune_steps: int):
                 adjoint_over_forward=round(t_bwd / t_fwd, 3),
                 fwd_plus_adjoint_particle_steps_per_s=2 * ps / (t_fwd + t_bwd),
                 estimator="causal score rows, lazy non-event flush",
-                grad=[float(x) for x in grad])
+                tuning=tuning, grad=[float(x) for x in grad])
 
 
 def sequential_leg(prob, batched_s: float):

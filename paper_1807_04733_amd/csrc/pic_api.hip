@@ -883,9 +883,11 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
   const Plan& p = c->plan;
   const bool fp64 = p.state_bytes == 8;
   const int n_slabs = (int)p.slab_inst.size();
-  int grid = c->tune.grid > 0 ? c->tune.grid : 512;
-  grid = std::max(1, std::min(grid, n_slabs));
+  // at most 256 threads per workgroup; the grid keeps the forward's number of waves
   const int block = std::min(c->tune.block, 256);
+  int grid = c->tune.grid > 0 ? c->tune.grid : 512;
+  grid = (int)std::min<int64_t>((int64_t)grid * c->tune.block / block, 1 << 16);
+  grid = std::max(1, std::min(grid, n_slabs));
   pic_status st = clear_particles(c);
   if (st != PIC_OK) return st;
   AdjArgs A;
@@ -903,7 +905,10 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
   ca.K = adj == 1 ? p.K : 0;
   ca.r = adj == 2 ? A.r : nullptr;
   // the replay advances one step per launch: z write-back at most every 4 steps and
-  // compaction at least every 8 (longer periods pay in the forward's two-step launches only)
+  // compaction at least every 8 (longer periods pay in the forward's two-step launches
+  // only), of slabs with at least 10 % dead slots (a compaction here also moves the
+  // carriers' score rows or partial returns)
+  ca.frac = std::max(ca.frac, 0.1f);
   const int K = std::max(1, std::min(c->tune.z_every, 4));
   const int compact_every =
       c->tune.compact_every > 0 ? std::min(c->tune.compact_every, 8) : 0;
@@ -1037,9 +1042,9 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
     if (st != PIC_OK) return st;
   }
   // stage 2: compaction cadence and threshold
-  for (int every : {4, 8, 16, 0}) {
-    for (float frac : {0.1f, 0.25f}) {
-      if (every == 0 && frac > 0.1f) continue;
+  for (int every : {8, 16, 32, 64, 0}) {
+    for (float frac : {0.05f, 0.1f, 0.25f}) {
+      if (every == 0 && frac != 0.1f) continue;
       pic_tuning t = win;
       t.compact_every = every;
       t.compact_frac = frac;
