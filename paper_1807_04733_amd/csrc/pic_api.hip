@@ -529,7 +529,7 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
       compact = compact || (c->tune.compact_every > 0 && (s + j + 1) % c->tune.compact_every == 0);
     if (compact && !c->plan.debug && s + ns < c->cfg.n_steps) {
       CompactArgs ca = compact_args(c);
-      HIP_TRY(launch_compact(ca, fp64, c->tune.block, c->stream));
+      HIP_TRY(launch_compact(ca, fp64, c->stream));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], c->stream));
     s += ns;
@@ -776,7 +776,7 @@ pic_status pic_compact(pic_ctx* c) {
   if (!c) return fail(PIC_EINVAL, "null context");
   if (c->plan.debug) return PIC_OK;  // debug runs keep every record in place
   CompactArgs ca = compact_args(c);
-  HIP_TRY(launch_compact(ca, c->plan.state_bytes == 8, c->tune.block, c->stream));
+  HIP_TRY(launch_compact(ca, c->plan.state_bytes == 8, c->stream));
   return PIC_OK;
 }
 
@@ -919,7 +919,7 @@ static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double
     HIP_TRY(launch_adjoint(A, fp64, adj, grid, block, c->stream));
     // carriers move with their score rows (causal) or partial returns (tree pass 1)
     if (compact_every > 0 && (n + 1) % compact_every == 0 && n + 1 < c->cfg.n_steps)
-      HIP_TRY(launch_compact(ca, fp64, 256, c->stream));
+      HIP_TRY(launch_compact(ca, fp64, c->stream));
   }
   A.s = step_args(c, c->cfg.n_steps - 1);
   HIP_TRY(launch_adjoint_final(A, fp64, adj, (uint32_t)c->cfg.n_steps, c->stream));

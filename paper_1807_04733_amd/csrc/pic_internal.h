@@ -183,7 +183,7 @@ struct StepLaunch {
 
 // launchers (pic_kernels.hip)
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s);
-hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, bool fp64, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& A, bool fp64, int adj, int grid, int block,
                           hipStream_t s);
 hipError_t launch_adjoint_final(const AdjArgs& A, bool fp64, int adj, uint32_t n_steps,

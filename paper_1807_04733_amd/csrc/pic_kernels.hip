@@ -824,78 +824,118 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   }
 }
 
-// In-place compaction of slabs whose tombstones exceed a fraction of their tail.  One
-// workgroup per slab walks it tile by tile: every lane loads its slot, a workgroup scan
-// of the live lanes gives the destination, and the stores follow a barrier, so a
-// destination (always <= its source) is never overwritten before it has been read.
+// In-place compaction of slabs whose tombstones exceed a fraction of their tail.  With L
+// live carriers in a slab, the live carriers at or above slot L move into the dead slots
+// below L and the tail becomes L, so about as many carriers move as there are tombstones
+// below L (the order of carriers in a slab changes no result).  One workgroup per slab
+// counts the live carriers, then collects dead slots below L and live slots at or above L
+// into two LDS rings, kScanTile slots per scan round, and moves them in pairs.  Sources
+// and destinations lie on either side of L, so the moves need no ordering among
+// themselves; the two counts are equal, so every dead slot below L is filled.
+constexpr int kCompactBlock = 256;
+constexpr int kCompactPer = 4;                                // slots per thread per round
+constexpr int kScanTile = kCompactBlock * kCompactPer;
+constexpr int kHoleBatch = 1024;                              // dead slots per move batch
+constexpr int kRingH = 2048;                                  // > kHoleBatch - 1 + kScanTile
+constexpr int kRingT = 4096;                                  // > kRingH - 1 + kScanTile
+static_assert(kHoleBatch - 1 + kScanTile <= kRingH && kRingH - 1 + kScanTile <= kRingT,
+              "ring bounds");
+
 template <typename F>
-__global__ void __launch_bounds__(1024) k_compact(CompactArgs a) {
-  __shared__ int s_w[16];
+__global__ void __launch_bounds__(kCompactBlock) k_compact(CompactArgs a) {
+  __shared__ int sH[kRingH], sT[kRingT];
+  __shared__ int s_cnt[3];  // appended dead slots, appended live slots, live carriers
   const int slab = blockIdx.x;
   const int tail = a.slab_tail[slab];
   const int dead = a.slab_dead[slab];
   if (tail == 0 || !((float)dead > a.frac * (float)tail)) return;
   const int64_t base = a.slab_base[slab];
-  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
+  const uint32_t* const fl = a.flags + base;
+  const int tid = threadIdx.x, lane = __lane_id();
+  if (tid < 3) s_cnt[tid] = 0;
+  __syncthreads();
+  {
+    int live = 0;
+    for (int tb = 0; tb < tail; tb += kScanTile) {
+      uint32_t f[kCompactPer];
+#pragma unroll
+      for (int j = 0; j < kCompactPer; ++j) {
+        const int t = tb + j * kCompactBlock + tid;
+        f[j] = t < tail ? fl[t] : kDead;
+      }
+#pragma unroll
+      for (int j = 0; j < kCompactPer; ++j) live += (f[j] & kDead) ? 0 : 1;
+    }
+    if (live) atomicAdd(&s_cnt[2], live);
+  }
+  __syncthreads();
+  const int L = s_cnt[2];
+  // wave-aggregated append of slot t to a ring (absolute positions; index = position & mask)
+  auto append = [&](bool want, int t, int* ring, int mask, int* ctr) {
+    const uint64_t m = __ballot(want);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int off = 0;
+    if (lane == leader) off = atomicAdd(ctr, __popcll(m));
+    off = __shfl(off, leader);
+    if (want) ring[(off + __popcll(m & lanes_below())) & mask] = t;
+  };
+  // one scan round over [from, from + kScanTile) ∩ [lo, hi): appends the slots whose dead
+  // bit equals `want_dead`; returns the ring's new end (the same in every thread)
+  auto scan = [&](int from, int hi, bool want_dead, int* ring, int mask, int* ctr) -> int {
+    uint32_t f[kCompactPer];
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const int t = from + j * kCompactBlock + tid;
+      f[j] = t < hi ? fl[t] : (want_dead ? 0u : kDead);
+    }
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j)
+      append(((f[j] & kDead) != 0) == want_dead, from + j * kCompactBlock + tid, ring, mask, ctr);
+    __syncthreads();
+    const int end = *ctr;
+    __syncthreads();  // every thread has read the count before the next round appends
+    return end;
+  };
   F* gz = (F*)a.z;
   F* gmu = (F*)a.mu;
-  int out = 0;
-  for (int tb = 0; tb < tail; tb += blockDim.x) {
-    const int t = tb + tid;
-    const bool have = t < tail;
-    uint32_t fl = have ? a.flags[base + t] : kDead;
-    const bool keep = !(fl & kDead);
-    F z = 0, mu = 0;
-    uint32_t E = 0;
-    uint64_t u = 0, ev = 0;
-    uint32_t wv = 0;
-    double row[kMaxCausalK];
-    double rr = 0.0;
-    if (keep) {
-      z = gz[base + t];
-      mu = gmu[base + t];
-      E = a.E[base + t];
-      u = a.uid[base + t];
-      if (a.ev) ev = a.ev[base + t];
-      if (a.w) wv = a.w[base + t];
-      if (a.S) {
-#pragma unroll
-        for (int k = 0; k < kMaxCausalK; ++k)
-          if (k < a.K) row[k] = a.S[(base + t) * a.K + k];
-      }
-      if (a.r) rr = a.r[base + t];
+  int hp = 0, tp = L;    // next slot to scan below L / at or above L
+  int hh = 0, ht = 0;    // dead slots below L waiting: ring positions [hh, ht)
+  int th = 0, tt = 0;    // live slots at or above L waiting: [th, tt)
+  for (;;) {
+    while (ht - hh < kHoleBatch && hp < L) {
+      ht = scan(hp, L, true, sH, kRingH - 1, &s_cnt[0]);
+      hp += kScanTile;
     }
-    const uint64_t m = __ballot(keep);
-    if (lane == 0) s_w[wave] = __popcll(m);
-    __syncthreads();
-    int woff = 0, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-      const int c = s_w[w];
-      woff += w < wave ? c : 0;
-      tot += c;
+    while (tt - th < ht - hh && tp < tail) {
+      tt = scan(tp, tail, false, sT, kRingT - 1, &s_cnt[1]);
+      tp += kScanTile;
     }
-    if (keep) {
-      const int64_t d = base + out + woff + __popcll(m & lanes_below());
-      gz[d] = z;
-      gmu[d] = mu;
-      a.E[d] = E;
-      a.uid[d] = u;
-      a.flags[d] = fl;
-      if (a.ev) a.ev[d] = ev;
-      if (a.w) a.w[d] = wv;
-      if (a.S) {
-#pragma unroll
-        for (int k = 0; k < kMaxCausalK; ++k)
-          if (k < a.K) a.S[d * a.K + k] = row[k];
-      }
-      if (a.r) a.r[d] = rr;
+    const int m = min(ht - hh, tt - th);
+    if (m == 0) break;
+    for (int i = tid; i < m; i += kCompactBlock) {
+      const int64_t src = base + sT[(th + i) & (kRingT - 1)];
+      const int64_t dst = base + sH[(hh + i) & (kRingH - 1)];
+      const F z = gz[src], mu = gmu[src];
+      const uint32_t E = a.E[src], f = a.flags[src];
+      const uint64_t u = a.uid[src];
+      gz[dst] = z;
+      gmu[dst] = mu;
+      a.E[dst] = E;
+      a.uid[dst] = u;
+      a.flags[dst] = f;
+      if (a.ev) a.ev[dst] = a.ev[src];
+      if (a.w) a.w[dst] = a.w[src];
+      if (a.S)
+        for (int k = 0; k < a.K; ++k) a.S[dst * a.K + k] = a.S[src * a.K + k];
+      if (a.r) a.r[dst] = a.r[src];
     }
-    out += tot;
-    __syncthreads();
+    hh += m;
+    th += m;
+    __syncthreads();  // the moved ring entries are read before later rounds reuse them
   }
   if (tid == 0) {
-    a.slab_tail[slab] = out;
+    a.slab_tail[slab] = L;
     a.slab_dead[slab] = 0;
   }
 }
@@ -979,12 +1019,12 @@ hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStr
   return e;
 }
 
-hipError_t launch_compact(const CompactArgs& a, bool fp64, int block, hipStream_t s) {
+hipError_t launch_compact(const CompactArgs& a, bool fp64, hipStream_t s) {
   if (a.n_slabs <= 0) return hipSuccess;
   if (fp64)
-    hipLaunchKernelGGL(k_compact<double>, dim3(a.n_slabs), dim3(block), 0, s, a);
+    hipLaunchKernelGGL(k_compact<double>, dim3(a.n_slabs), dim3(kCompactBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_compact<float>, dim3(a.n_slabs), dim3(block), 0, s, a);
+    hipLaunchKernelGGL(k_compact<float>, dim3(a.n_slabs), dim3(kCompactBlock), 0, s, a);
   return hipGetLastError();
 }
 
