@@ -67,6 +67,22 @@ def test_gradient_matches_oracle_bilayer(torch_gpu, oracle_mod, estimator):
 
 
 @pytest.mark.parametrize("estimator", [0, 1])
+def test_gradient_with_compaction_every_step(torch_gpu, oracle_mod, estimator):
+    """The forward and the replay compact after every step (the replay only slabs with at
+    least 10 % tombstones), moving score rows (causal) or partial returns (whole-tree) with
+    the carriers that fill the tombstones; the gradient still equals the oracle's."""
+    prob = W.config3(n_primaries=5000, n_steps=90)
+    prob.e_min_fx = W.e_fx(0.3)
+    gd, gc = _random_g(prob, 5)
+    g = _gpu_grad(prob, gd, gc, estimator, slab_primaries=500, capacity_factor=30,
+                  tuning={"compact_every": 1, "compact_frac": 0.0})
+    ref = oracle_mod.run(prob, g_dens=gd, g_cur=gc, grad_per_tree=bool(estimator)).grad
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert np.abs(g - ref).max() <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("estimator", [0, 1])
 def test_gradient_matches_oracle_removal_at_next_event(torch_gpu, oracle_mod, estimator):
     prob = W.config3(n_primaries=5000, n_steps=90)
     prob.e_min_fx = W.e_fx(0.3)

@@ -270,6 +270,37 @@ def test_extended_modes_without_debug(torch_gpu, oracle_mod, kind):
     assert_parity(dev, ref, prob)
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_compaction_every_step_records(torch_gpu, oracle_mod, fp64):
+    """Compaction after every step of every slab that has a tombstone, on a workload where
+    most carriers die (E_min = 0.4 eV): the live carriers above each new tail fill the
+    tombstones below it, moving their weights along.  Bins and counters equal the
+    oracle's, and so do the records of the live carriers (compaction drops the dead ones;
+    debug runs, which keep every record, never compact)."""
+    prob = W.variant(W.config1(parallel=True, n_primaries=6000, n_steps=140),
+                     weights=True)
+    prob.e_min_fx = W.e_fx(0.4)
+    prob.state_fp64 = fp64
+    dev, ref = run_both(prob, oracle_mod, debug=False, slab_primaries=300,
+                        tuning={"sub_steps": 2, "z_every": 2, "compact_every": 1,
+                                "compact_frac": 0.0})
+    parts = dev["parts"]
+    dev["parts"] = None
+    assert_parity(dev, ref, prob)
+    keep_d = ~parts["dead"]
+    keep_r = ref.records["dead"] < 0
+    live_d = {k: v[keep_d] for k, v in parts.items()}
+    live_r = {k: v[keep_r] for k, v in ref.records.items()}
+    assert len(live_d["uid"]) == len(live_r["uid"])
+    r = compare_records(live_d, live_r, fp64, z_tol=1e-9 if fp64 else 0.0)
+    _say(f"[parity] live records: joined {r['joined']} of {r['n_ref']}, match {r['frac']:.6f}")
+    assert r["joined"] >= 0.999 * r["n_ref"]
+    assert r["frac"] >= 0.9999, r["bad"]
+    # most carriers died, and compaction removed them
+    assert keep_r.sum() < 0.5 * len(ref.records["uid"])
+    assert len(parts["uid"]) < 0.55 * len(ref.records["uid"])
+
+
 def test_fp64_state_with_tables_and_weights(torch_gpu, oracle_mod):
     """Binary64 particle state with energy tables and weights (records to 1e-9 nm)."""
     prob = W.variant(W.config0(n_primaries=2500, n_steps=100), energy_tables=True,
