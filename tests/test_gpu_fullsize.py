@@ -94,3 +94,41 @@ def test_adjoint_workload_forward_full(torch_gpu, oracle_mod):
 
 def test_multilayer_tables_full(torch_gpu, oracle_mod):
     run_full(W.config4(), 30, oracle_mod)
+
+
+def test_multilayer_tables_adjoint_full(torch_gpu, oracle_mod):
+    """Whole-tree adjoint of the full multilayer workload (2e8 primaries; 260 parameters:
+    tau0 per channel and the nodes of the T(E) tables) with loss weights on the bins of the
+    first 40 steps only.  Only the trees injected before step 40 then have a non-zero
+    return, so the oracle, following exactly those trees over the whole run (their scores
+    span all 2000 steps), must give the same gradient."""
+    import torch
+    from paper_1807_04733_amd import PicSim
+    prob = W.config4()
+    cut = 40
+    rng = np.random.default_rng(11)
+    gd, gc = [], []
+    for i in range(len(prob.instances)):
+        d = rng.normal(size=prob.dens_shape(i)) * (rng.uniform(size=prob.dens_shape(i)) < 0.2)
+        d[(cut + prob.dens_stride - 1) // prob.dens_stride:] = 0.0
+        c = rng.normal(size=prob.cur_shape(i)) * (rng.uniform(size=prob.cur_shape(i)) < 0.2)
+        c[(cut + prob.cur_stride - 1) // prob.cur_stride:] = 0.0
+        gd.append(d)
+        gc.append(c)
+    roots = int(prob.instances[0].sched[:cut].sum())
+    assert all(int(it.sched[:cut].sum()) == roots for it in prob.instances)
+    _say(f"[fullsize] {prob.name}: whole-tree adjoint, loss on steps < {cut} "
+         f"({roots} trees per instance)")
+    sim = PicSim(prob, adjoint=2)
+    sim.step()
+    sim.counters()
+    g = sim.backward(gd, gc, 1)
+    sim.close()
+    torch.cuda.empty_cache()
+    ref = oracle_mod.run(prob, root_range=(0, roots), g_dens=gd, g_cur=gc,
+                         grad_per_tree=True).grad
+    scale = np.abs(ref).max()
+    _say(f"[fullsize] gradient: {int((ref != 0).sum())} non-zero of {ref.size}, "
+         f"max |diff| / max |ref| = {np.abs(g - ref).max() / scale:.3e}")
+    assert roots * len(prob.instances) > 10000 and scale > 0
+    assert np.abs(g - ref).max() <= 1e-9 * scale
