@@ -236,9 +236,11 @@ pic_status pic_generations(pic_ctx* ctx, double* gen_out);
  * device arrays laid out like pic_deposit's outputs (either may be NULL).  Parameter
  * order: ln tau0 of channels 0..n_channels-1, then T[t][e] row-major.  The result is an
  * unbiased Monte-Carlo estimate on the same random streams as the forward run.  The
- * replay advances one step per launch, writes z back every min(z_every, 4) steps and
- * compacts every min(compact_every, 8) steps (compact_every 0: never), moving score rows
- * (causal) and partial returns (whole-tree) with their carriers.  Synchronizes. */
+ * replay advances one step per launch in workgroups of at most 256 threads (the grid
+ * scaled to keep the tuning's number of waves), writes z back every min(z_every, 4) steps
+ * and compacts every min(compact_every, 8) steps (compact_every 0: never) the slabs whose
+ * dead slots exceed max(compact_frac, 0.1) of their tail, moving score rows (causal) and
+ * partial returns (whole-tree) with their carriers.  Synchronizes. */
 pic_status pic_backward(pic_ctx* ctx, const double* g_dens, const double* g_cur,
                         double* grad_out, int32_t estimator);
 
