@@ -301,6 +301,34 @@ def test_compaction_every_step_records(torch_gpu, oracle_mod, fp64):
     assert len(parts["uid"]) < 0.55 * len(ref.records["uid"])
 
 
+def test_explicit_compaction_between_calls(torch_gpu, oracle_mod):
+    """pic_compact between two pic_step calls (every slab with a tombstone, since
+    compact_frac is 0): afterwards the slabs hold exactly their live carriers, and the
+    run's bins and counters still equal the oracle's."""
+    from paper_1807_04733_amd import PicSim
+    prob = W.config1(parallel=False, n_primaries=5000, n_steps=100)
+    prob.e_min_fx = W.e_fx(0.3)
+    ref = oracle_mod.run(prob)
+    sim = PicSim(prob, slab_primaries=400,
+                 tuning={"compact_every": 0, "compact_frac": 0.0, "sub_steps": 2,
+                         "z_every": 4})
+    sim.step(37)
+    before = sim.particles()
+    assert before["dead"].any()
+    sim.compact()
+    after = sim.particles()
+    assert not after["dead"].any()
+    assert len(after["uid"]) == int((~before["dead"]).sum())
+    assert np.array_equal(np.sort(after["uid"]), np.sort(before["uid"][~before["dead"]]))
+    sim.step(63)
+    dens, cur = sim.int_bins()
+    cnt = sim.counters()
+    sim.close()
+    assert np.array_equal(dens[0], ref.dens[0])
+    assert np.array_equal(cur[0], ref.cur[0])
+    assert np.array_equal(cnt, ref.counters)
+
+
 def test_fp64_state_with_tables_and_weights(torch_gpu, oracle_mod):
     """Binary64 particle state with energy tables and weights (records to 1e-9 nm)."""
     prob = W.variant(W.config0(n_primaries=2500, n_steps=100), energy_tables=True,
