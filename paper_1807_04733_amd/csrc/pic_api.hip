@@ -333,9 +333,27 @@ void drop_graph(pic_ctx* c) {
 // weighted run, u32 counts otherwise
 size_t dens_elem(const pic_ctx* c) { return c->plan.off_w >= 0 ? 8 : 4; }
 
+// LDS bytes per compute unit (160 KB on gfx950).
+size_t lds_per_cu() {
+  static size_t cached = 0;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cached) return cached;
+  int dev = 0, bytes = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess &&
+      bytes > 0)
+    cached = (size_t)bytes;
+  else
+    cached = 160 * 1024;
+  return cached;
+}
+
 // Dynamic LDS layout of one step launch over n_sub sub-steps: the density slices (of the
-// sub-steps that deposit density, when density goes to LDS), the current slices, then the
-// per-wave queues.  Fills the offsets in `a` (if given) and returns the bytes.
+// sub-steps that deposit density, when density goes to LDS), the current slices, the
+// per-wave queues, then (where they fit) the per-wave copies of the sub-step-0 queue's
+// carrier state.  Fills the offsets in `a` (if given) and returns the bytes.
 size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, const int* cur_on,
                    StepArgs* a) {
   size_t off = 0;
@@ -362,7 +380,17 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
     a->lds_q_at = (int32_t)off;
     a->lds_q_bytes = (int32_t)step_queue_bytes(n_sub);
   }
-  return off + (size_t)(block / 64) * step_queue_bytes(n_sub);
+  off += (size_t)(block / 64) * step_queue_bytes(n_sub);
+  // copies of the sub-step-0 queue's carrier state, when they fit without costing a
+  // workgroup per CU (at most 16 waves of the step kernel per CU, its register limit)
+  const size_t stage_at = (off + 15) & ~(size_t)15;
+  const size_t stage_end =
+      stage_at + (size_t)(block / 64) * stage_wave_bytes(c->plan.state_bytes == 8);
+  const size_t per_wg = lds_per_cu() / (size_t)std::max(1, 16 / (block / 64));
+  const size_t stat = step_static_lds();
+  const bool stage = stage_end + stat <= per_wg && stage_end <= c->max_lds;
+  if (a) a->lds_stage_at = stage ? (int32_t)stage_at : -1;
+  return stage ? stage_end : off;
 }
 
 // LDS of a one-step launch that deposits both moments (the largest one-step layout).
@@ -419,6 +447,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.etab_words = p.etab_max;
   a.wt = c->at<uint32_t>(p.off_w);
   a.lds_etab_at = -1;
+  a.lds_stage_at = -1;
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
   a.n_ebins = c->cfg.n_ebins;

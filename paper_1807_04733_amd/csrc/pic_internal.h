@@ -133,6 +133,9 @@ struct StepArgs {
   int32_t lds_etab_at, etab_words;
   // superparticle weights (2^-16 units) per slot, or null: the moments are plain counts
   uint32_t* wt;
+  // per-wave copies of the state of the carriers in the sub-step-0 queue (stage_wave_bytes
+  // per wave), so that their general pass reads LDS instead of HBM; -1: not staged
+  int32_t lds_stage_at;
 };
 
 struct AdjArgs {
@@ -173,6 +176,10 @@ constexpr size_t kSlowQueueBytes = 128 * 4;
 constexpr size_t step_queue_bytes(int n_sub) {
   return kChildQueueBytes + 128 * 4 + (n_sub > 1 ? 256 * 4 : 0);
 }
+
+// bytes per wave of the staged sub-step-0 queue: z and cos(theta) (binary32 or binary64),
+// E, flags and uid of each of its 128 entries
+constexpr size_t stage_wave_bytes(bool fp64) { return 128 * ((fp64 ? 16 : 8) + 16); }
 
 // Launch shape of one step.
 struct StepLaunch {

@@ -244,6 +244,16 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   ChildQueue& Q = *(ChildQueue*)wq;
   uint32_t* const SQ0 = (uint32_t*)(wq + kChildQueueBytes);
   uint32_t* const SQ1 = SQ0 + kSlowQ0;
+  // copies of the state of the carriers in SQ0, entry for entry (when staged): z, cos(theta),
+  // E, flags, uid as they are stored in the particle arrays
+  const bool STG = a.lds_stage_at >= 0;
+  static_assert(stage_wave_bytes(sizeof(F) == 8) == kSlowQ0 * (2 * sizeof(F) + 16), "stage");
+  F* const st_z = (F*)(dyn + (STG ? a.lds_stage_at : 0) +
+                       (size_t)wave * stage_wave_bytes(sizeof(F) == 8));
+  F* const st_mu = st_z + kSlowQ0;
+  uint32_t* const st_E = (uint32_t*)(st_mu + kSlowQ0);
+  uint32_t* const st_fl = st_E + kSlowQ0;
+  uint64_t* const st_u = (uint64_t*)(st_fl + kSlowQ0);
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   const double* const et = ET ? (const double*)(dyn + a.lds_etab_at) : nullptr;
   const bool tau2 = a.tau_exp2 != 0;
@@ -318,18 +328,35 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
 
-    // ---- put the slots of the lanes with `pred` into the queue of sub-step J
-    auto push = [&](auto sub, bool pred, uint32_t slot) __attribute__((always_inline)) {
-      constexpr int J = decltype(sub)::value;
+    // ---- put the slots of the lanes with `pred` into the queue of sub-step 0 with a copy
+    // of their stored state (z, cos(theta), E, flags, uid) when the queue is staged
+    auto push0 = [&](bool pred, uint32_t slot, F z, F mu, uint32_t E, uint32_t fl,
+                     uint64_t u) __attribute__((always_inline)) {
       const uint64_t m = __ballot(pred);
       if (m) {
-        if (J == 0) {
-          if (pred) SQ0[sn0 + prefix_count(m)] = slot;
-          sn0 += __popcll(m);
-        } else {
-          if (pred) SQ1[sn1 + prefix_count(m)] = slot;
-          sn1 += __popcll(m);
+        if (pred) {
+          const int q = sn0 + prefix_count(m);
+          SQ0[q] = slot;
+          if (STG) {
+            st_z[q] = z;
+            st_mu[q] = mu;
+            st_E[q] = E;
+            st_fl[q] = fl;
+            st_u[q] = u;
+          }
+          n_left[0] += 1;
         }
+        sn0 += __popcll(m);
+      }
+    };
+    // ---- put the slots of the lanes with `pred` into the queue of sub-step J >= 1
+    auto push = [&](auto sub, bool pred, uint32_t slot) __attribute__((always_inline)) {
+      constexpr int J = decltype(sub)::value;
+      static_assert(J > 0, "sub-step 0 entries go through push0");
+      const uint64_t m = __ballot(pred);
+      if (m) {
+        if (pred) SQ1[sn1 + prefix_count(m)] = slot;
+        sn1 += __popcll(m);
         if (pred) n_left[J] += 1;
       }
     };
@@ -586,21 +613,44 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     };
 
     // re-read the top n slots of a sub-step's queue and bring z to the start of that step
-    auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, uint32_t& g, double& z,
-                         double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo, uint32_t& hi,
-                         uint64_t& evp, uint32_t& wfx) __attribute__((always_inline)) -> bool {
+    auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, bool staged, uint32_t& g,
+                         double& z, double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo,
+                         uint32_t& hi, uint64_t& evp, uint32_t& wfx)
+                         __attribute__((always_inline)) -> bool {
       wave_sync();
       const bool act = lane < n;
-      g = act ? SQ[sn - n + lane] : 0u;
+      const int q = sn - n + lane;
+      g = act ? SQ[q] : 0u;
+      // the queue entries (and their staged copies) are read before any later push
+      // reuses them
+      F sz = 0, smu = 0;
+      uint32_t sE = 0, sfl = kDead;
+      uint64_t su = 0;
+      if (staged && act) {
+        sz = st_z[q];
+        smu = st_mu[q];
+        sE = st_E[q];
+        sfl = st_fl[q];
+        su = st_u[q];
+      }
       sn -= n;
       wave_sync();
       fl = kDead;
       if (act) {
-        fl = at(sp.fl, g);
-        z = (double)at(sp.z, g);
-        mu = (double)at(sp.mu, g);
-        E = at(sp.E, g);
-        const uint64_t u = at(sp.uid, g);
+        uint64_t u;
+        if (staged) {
+          fl = sfl;
+          z = (double)sz;
+          mu = (double)smu;
+          E = sE;
+          u = su;
+        } else {
+          fl = at(sp.fl, g);
+          z = (double)at(sp.z, g);
+          mu = (double)at(sp.mu, g);
+          E = at(sp.E, g);
+          u = at(sp.uid, g);
+        }
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
         if (DEBUG) evp = at(sp.ev, g);
@@ -621,7 +671,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       double z = 0.0, mu = 0.0;
       uint64_t evp = 0;
       const bool act = pop_state(T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
-                                 a.sub_z_phase[T - 1], g, z, mu, E, fl, lo, hi, evp, wfx);
+                                 a.sub_z_phase[T - 1], T == 1 && STG, g, z, mu, E, fl, lo, hi,
+                                 evp, wfx);
       general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
       drain_kids(Sub<T - 1>{});
     };
@@ -633,7 +684,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         double z = 0.0, mu = 0.0;
         uint64_t evp = 0;
         const bool act =
-            pop_state(SQ0, sn0, n, a.sub_z_phase[0], g, z, mu, E, fl, lo, hi, evp, wfx);
+            pop_state(SQ0, sn0, n, a.sub_z_phase[0], STG, g, z, mu, E, fl, lo, hi, evp, wfx);
         const bool surv =
             general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
         cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi, wfx);
@@ -653,6 +704,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       off = __shfl(off, leader);
       bool placed = false;
       uint32_t pos = 0;
+      F qz = 0, qmu = 0;  // the stored state, for the staged sub-step-0 queue
+      uint32_t qE = 0, qfl = 0;
+      uint64_t qu = 0;
       if (want) {
         pos = (uint32_t)(tail0 + off + prefix_count(m));
         const int64_t j = kk + S * (f0 + k);
@@ -681,17 +735,25 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         }
         if ((int)pos < cap) {
           placed = true;
-          at(sp.z, pos) = (F)z;
-          at(sp.mu, pos) = (F)mu;
-          at(sp.E, pos) = E;
-          at(sp.uid, pos) = (uint64_t)root;
-          at(sp.fl, pos) = fl;
+          qz = (F)z;
+          qmu = (F)mu;
+          qE = E;
+          qfl = fl;
+          qu = (uint64_t)root;
+          at(sp.z, pos) = qz;
+          at(sp.mu, pos) = qmu;
+          at(sp.E, pos) = qE;
+          at(sp.uid, pos) = qu;
+          at(sp.fl, pos) = qfl;
           if (DEBUG) at(sp.ev, pos) = 0;
         } else {
           atomicOr(a.status, kStOverflow);
         }
       }
-      push(sub, placed, pos);
+      if constexpr (J == 0)
+        push0(placed, pos, qz, qmu, qE, qfl, qu);
+      else
+        push(sub, placed, pos);
     };
 
     // The slot a lane will handle in its next iteration is fetched one iteration ahead,
@@ -775,7 +837,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
             if (st) at(sp.fl, gi) = rfl & ~(kStampMask << kStampShift);
           }
         }
-        push(Sub<0>{}, left_at == 0, gi);
+        push0(left_at == 0, gi, rz, rmu, rE, rfl, ru);
         if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi);
         // ---- new primaries of each sub-step
         inject(Sub<0>{}, is_new0, f00, t - tail0);
