@@ -29,6 +29,9 @@
 namespace pic {
 
 constexpr int kSlowQ = (int)(kSlowQueueBytes / 4);  // general-path slots per wave queue
+// bytes per wave of the copies of the queued carriers' stored state
+template <typename F>
+constexpr size_t kAdjStageBytes = (size_t)kSlowQ * (2 * sizeof(F) + 20);
 constexpr int kNfShift = 16;
 constexpr uint32_t kNfMask = 0x7FFFu;
 
@@ -185,6 +188,10 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       (uint32_t*)((unsigned char*)s_gcur + (((size_t)a.lds_cur_words * 8 + 15) & ~(size_t)15));
   double* const s_etab = (double*)((unsigned char*)s_slow + (blockDim.x / 64) * kSlowQueueBytes);
   const double* const et = a.etab ? s_etab : nullptr;
+  // then, per wave, copies of the stored state of the carriers in its queue (z, cos(theta),
+  // E, flags, weight, uid), so that their general pass reads LDS instead of HBM
+  unsigned char* const s_stage =
+      (unsigned char*)s_etab + (((a.etab ? (size_t)a.etab_words * 8 : 0) + 15) & ~(size_t)15);
   const bool tau2 = a.tau_exp2 != 0;
   __shared__ DevInst s_inst;
   __shared__ double s_grad[kMaxK];
@@ -199,6 +206,12 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
   // stamp of every z this step stores (0 when the step ends a write-back period)
   const uint32_t z_next = a.z_write ? 0u : (uint32_t)a.z_phase + 1u;
   uint32_t* SQ = s_slow + wave * kSlowQ;
+  F* const st_z = (F*)(s_stage + (size_t)wave * kAdjStageBytes<F>);
+  F* const st_mu = st_z + kSlowQ;
+  uint32_t* const st_E = (uint32_t*)(st_mu + kSlowQ);
+  uint32_t* const st_fl = st_E + kSlowQ;
+  uint32_t* const st_w = st_fl + kSlowQ;
+  uint64_t* const st_u = (uint64_t*)(st_w + kSlowQ);
   const AdjOps<ADJ> ops{A, s_grad};
   int cur_inst = -1;
   bool bad = false;
@@ -377,22 +390,23 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    // finish the top n queued general-path slots (state re-read from HBM)
+    // finish the top n queued general-path slots (their stored state from the LDS copy)
     auto drain_slow = [&](int n) {
       wave_sync();
       const bool act = lane < n;
-      const uint32_t t = act ? SQ[sn - n + lane] : 0u;
+      const int q = sn - n + lane;
+      const uint32_t t = act ? SQ[q] : 0u;
       sn -= n;
       const int64_t g = base + t;
       uint32_t fl = kDead, E = 0, lo = 0, hi = 0, wfx = 1u << 16;
       double z = 0.0, mu = 0.0;
       if (act) {
-        fl = a.flags[g];
-        if (a.wt) wfx = a.wt[g];
-        z = (double)gz[g];
-        mu = (double)gmu[g];
-        E = a.E[g];
-        const uint64_t u = a.uid[g];
+        fl = st_fl[q];
+        wfx = st_w[q];
+        z = (double)st_z[q];
+        mu = (double)st_mu[q];
+        E = st_E[q];
+        const uint64_t u = st_u[q];
         lo = (uint32_t)u;
         hi = (uint32_t)(u >> 32);
         const int d = a.z_phase - (int)((fl >> kStampShift) & kStampMask);
@@ -505,7 +519,16 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       // ---- queue the general-path slots
       const uint64_t ms = __ballot(slow);
       if (ms) {
-        if (slow) SQ[sn + prefix_count(ms)] = (uint32_t)t;
+        if (slow) {
+          const int q = sn + prefix_count(ms);
+          SQ[q] = (uint32_t)t;
+          st_z[q] = rz;
+          st_mu[q] = rmu;
+          st_E[q] = rE;
+          st_fl[q] = rfl;
+          st_w[q] = rw;
+          st_u[q] = ru;
+        }
         sn += __popcll(ms);
       }
       if (sn >= 64) drain_slow(64);
@@ -572,7 +595,8 @@ template <typename F>
 static hipError_t launch_adj_prec(const AdjArgs& A, int adj, int grid, int block, hipStream_t s) {
   const size_t lds = (((size_t)A.s.lds_cur_words * 8 + 15) & ~(size_t)15) +
                      (size_t)(block / 64) * kSlowQueueBytes +
-                     (A.s.etab ? (size_t)A.s.etab_words * 8 : 0);
+                     (((A.s.etab ? (size_t)A.s.etab_words * 8 : 0) + 15) & ~(size_t)15) +
+                     (size_t)(block / 64) * kAdjStageBytes<F>;
   switch (adj) {
     case 1: hipLaunchKernelGGL((k_adj<F, 1>), dim3(grid), dim3(block), lds, s, A); break;
     case 2: hipLaunchKernelGGL((k_adj<F, 2>), dim3(grid), dim3(block), lds, s, A); break;
