@@ -203,7 +203,8 @@ constexpr int kSlowQ1 = 256;
 // (which is above p = 1 - exp(-x), so no event can happen).  The first step that leaves
 // the common path puts the carrier's slot into the wave's LDS queue of that sub-step; the
 // state in HBM is still the one stored before it (its z stamp says which straight
-// flights to redo).  A queue of 64 slots runs the general path as a full wave; the
+// flights to redo), and the sub-step-0 queue keeps a copy of it in LDS where that fits.
+// A queue of 64 slots runs the general path as a full wave; the
 // survivors and newborns of a sub-step-0 general pass continue with sub-step 1 the same
 // way.  New primaries (source term, Eq. 17) of a sub-step are appended with their initial
 // state and queued for its general path.
@@ -212,7 +213,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   constexpr bool ET = (MODE & kModeTab) != 0;
   // dynamic LDS: [histogram slices of the sub-steps | energy tables | per wave: newborn
-  // queue, slot queue of sub-step 0 (, of sub-step 1)]; offsets set by the host
+  // queue, slot queue of sub-step 0 (, of sub-step 1) | per wave, where they fit: copies of
+  // the stored state of the sub-step-0 queue's carriers]; offsets set by the host
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ DevInst s_inst;
   __shared__ unsigned long long s_cnt[T][kNC];
