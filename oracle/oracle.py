@@ -63,6 +63,7 @@ class _Problem(C.Structure):
         ("dens_stride", C.c_int32), ("cur_stride", C.c_int32),
         ("root_lo", C.c_int64), ("root_hi", C.c_int64), ("n_threads", C.c_int32),
         ("absorb_next", C.c_int32), ("weighted", C.c_int32),
+        ("script", C.POINTER(C.c_uint32)), ("n_script", C.c_int64),
     ]
 
 
@@ -129,7 +130,8 @@ class OracleResult:
 
 def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
         root_range=None, n_threads: int = 0, g_dens=None, g_cur=None,
-        grad_per_tree: bool = False, gen: Optional[bool] = None) -> OracleResult:
+        grad_per_tree: bool = False, gen: Optional[bool] = None,
+        script=None) -> OracleResult:
     """Simulate `problem` (a workloads.Problem) on the CPU.
 
     root_range=(lo, hi) restricts every instance to its local roots lo..hi-1 (trees are
@@ -137,7 +139,9 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
     (lists of arrays shaped like the bins) switch on the likelihood-ratio gradient of
     sum(g_dens*dens) + sum(g_cur*cur_float) with respect to (ln tau0 per channel, T table
     entries).  gen (default: problem.gen_moment) also returns the generation moment: the
-    sum of the generation labels per (density slot, depth, spin).
+    sum of the generation labels per (density slot, depth, spin).  script: rows of 8
+    uint32 (a Philox counter, then the 4 words to return for it) that replace the
+    generator's words for the listed counters (white-box tests).
     """
     lib = _load()
     if gen is None:
@@ -201,6 +205,10 @@ def run(problem, *, records: bool = False, rec_cap: Optional[int] = None,
     P.n_threads = n_threads
     P.absorb_next = int(bool(getattr(problem, "absorb_next", False)))
     P.weighted = int(bool(getattr(problem, "weighted", False)))
+    if script is not None:
+        sc = arr(np.asarray(script, np.uint32).reshape(-1, 8), np.uint32)
+        P.script = _ptr(sc, C.c_uint32)
+        P.n_script = sc.shape[0]
 
     nd = [int(np.prod(problem.dens_shape(i))) for i in range(len(problem.instances))]
     nc = [int(np.prod(problem.cur_shape(i))) for i in range(len(problem.instances))]

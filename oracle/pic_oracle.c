@@ -68,6 +68,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 static void draw(const orc_problem* P, uint32_t uid_lo, uint32_t uid_hi, uint32_t step,
                  uint32_t tag, uint32_t w[4]) {
   uint32_t ctr[4] = {uid_lo, uid_hi, step, tag};
+  for (int64_t i = 0; i < P->n_script; ++i) {   /* scripted words, if this counter is listed */
+    const uint32_t* e = P->script + 8 * i;
+    if (e[0] == ctr[0] && e[1] == ctr[1] && e[2] == ctr[2] && e[3] == ctr[3]) {
+      memcpy(w, e + 4, 4 * sizeof(uint32_t));
+      return;
+    }
+  }
   uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
   orc_philox4x32_10(ctr, key, w);
 }

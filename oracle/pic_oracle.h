@@ -77,6 +77,11 @@ typedef struct {
   int32_t weighted;           /* 1: the moments are sums over carriers of their weight
                                  (density and generation label in 2^-16 units, current
                                  rint(v cos(theta) w 2^32)); 0: plain counts */
+  /* Scripted random numbers (white-box tests): n_script entries of 8 words, a Philox
+   * counter (4 words) and the 4 words to return for it instead of the generator's; every
+   * counter not listed draws from Philox as usual.  NULL / 0: off. */
+  const uint32_t* script;
+  int64_t n_script;
 } orc_problem;
 
 typedef struct {

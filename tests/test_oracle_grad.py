@@ -120,3 +120,83 @@ def test_transmission_gradient_vs_crn_differences(oracle_lib, per_tree):
     m_fd, se_fd = _seeds(fd, 8)
     assert abs(m_lr - m_fd) < 4 * math.hypot(se_lr, se_fd), (m_lr, se_lr, m_fd, se_fd)
     assert abs(m_fd) > 4 * se_fd          # the derivative is resolved at all
+
+
+@pytest.mark.parametrize("per_tree", [False, True])
+def test_gradient_with_elastic_channel_closed_form(oracle_lib, per_tree):
+    """Constant lifetimes with an elastic channel (tau_el = 30 fs, Eq. 8) and E_min = 0.  A
+    step splits a carrier with probability p q: p = 1 - exp(-x), x = dt (1/tau0 + 1/tau_el)
+    (Eq. 2), and q = (1/tau0) / (1/tau0 + 1/tau_el) the inelastic share of the events
+    (Eq. 5); an elastic event only turns the carrier.  So E[N_alive after n steps] =
+    (1 + p q)^n per primary and d/d ln tau0 = n (1 + p q)^(n-1) d(pq)/d ln tau0, with
+    dp/d ln tau0 = -x_in e^-x (x_in = dt / tau0) and dq/d ln tau0 = q (q - 1)."""
+    n, dt, tau, tel, N = 20, 1.0, 20.0, 30.0, 6000
+    x_in, x = dt / tau, dt * (1.0 / tau + 1.0 / tel)
+    p = -math.expm1(-x)
+    q = (1.0 / tau) / (1.0 / tau + 1.0 / tel)
+    dpq = q * (-x_in * math.exp(-x)) + p * q * (q - 1.0)
+    exact = np.array([(1 + p * q) ** n, n * (1 + p * q) ** (n - 1) * dpq])
+
+    def one(seed):
+        prob = W.homogeneous(thickness=60.0, n_primaries=N, n_steps=n, tau0=tau, tau_el=tel,
+                             tau_exp=0, dt=dt, e_min_ev=0.0, seed=seed)
+        gd = np.zeros(prob.dens_shape(0))
+        gd[-1] = 1.0
+        res = oracle_lib.run(prob, g_dens=[gd], grad_per_tree=per_tree)
+        g = res.grad
+        return [res.counters[-1, 9] / N, (g[W.AU_UP] + g[W.AU_DN]) / N]
+
+    m, se = _seeds(one, 10)
+    assert np.all(np.abs(m - exact) < 4 * se), (m, exact, se)
+    # the elastic events happen at the expected share of all events
+    prob = W.homogeneous(thickness=60.0, n_primaries=N, n_steps=n, tau0=tau, tau_el=tel,
+                         tau_exp=0, dt=dt, e_min_ev=0.0, seed=99)
+    c = oracle_lib.run(prob).counters
+    ee, el = c[:, 1].sum(), c[:, 2].sum()
+    assert abs(el / (ee + el) - (1 - q)) < 4 * math.sqrt(q * (1 - q) / (ee + el))
+
+
+def _first_hit_problem(E_ev, table, N, seed):
+    """Fe(15)/Au(1000), carriers injected uniformly in Fe at one energy, tau -> infinity,
+    45 fs: a carrier covers at most 27 nm in Fe, so it meets the interface at most once,
+    and a transmitted carrier never comes back from the thick Au layer."""
+    inf = float("inf")
+    inst = W.make_instance(W.bilayer(15.0, 1000.0), n_primaries=N, n_steps=45,
+                           T_tables=np.stack([table] * 4), T_emax=2.0,
+                           tau0=(inf, inf, inf, inf), e0_ev=(E_ev, E_ev), src_lambda=0.0,
+                           dz=5.0)
+    return W.Problem([inst], seed=seed, dt=1.0, n_steps=45, state_fp64=True)
+
+
+@pytest.mark.parametrize("per_tree", [False, True])
+@pytest.mark.parametrize("k,f", [(8, 0.25), (45, 0.6)])
+def test_transmission_table_gradient_split_between_nodes(oracle_lib, per_tree, k, f):
+    """64-node transmission tables, carriers that meet the interface at most once (one
+    energy between nodes k and k+1, weights 1-f and f): the expected number of carriers in
+    Au at the end is N_hit T(E) with T(E) = (1-f) T_k + f T_(k+1), and N_hit, the number of
+    first hits, does not depend on T.  So the gradient is N_hit (1-f) on node k and
+    N_hit f on node k+1 (summed over the Fe->Au tables of both spins) and exactly 0 on
+    every other node and on the Au->Fe tables.  The estimate's standard error per hit is
+    w sqrt(1/T - 1)."""
+    table = 0.5 + 0.3 * np.sin(np.arange(64) * 1.7)
+    prob = _first_hit_problem((k + f) * 2.0 / 63, table, 12000, seed=3)
+    gd = np.zeros(prob.dens_shape(0))
+    gd[-1, 3:] = 1.0                        # depth bins of Au (5 nm each, Au from 15 nm)
+    res = oracle_lib.run(prob, g_dens=[gd], grad_per_tree=per_tree)
+    names = oracle_lib.COUNTER_NAMES
+    nh = int(res.counters[:, names.index("transmit")].sum() +
+             res.counters[:, names.index("refl_if")].sum())
+    assert nh > 4000
+    C = prob.instances[0].n_channels
+    g = res.grad[C:].reshape(4, 64)
+    x = float(prob.instances[0].src_e_lo[0]) * 2.0 ** -30 * (63 / 2.0)
+    fr = x - math.floor(x)
+    T = table[k] + (table[k + 1] - table[k]) * fr
+    for node, w in ((k, 1.0 - fr), (k + 1, fr)):
+        got = g[0, node] + g[1, node]
+        se = w * math.sqrt(nh * (1.0 / T - 1.0))
+        assert abs(got - nh * w) < 4 * se, (node, got, nh * w, se)
+    mask = np.ones((4, 64), bool)
+    mask[:2, [k, k + 1]] = False
+    assert np.all(g[mask] == 0.0)
+    assert np.all(res.grad[:C] == 0.0)      # nothing scatters
