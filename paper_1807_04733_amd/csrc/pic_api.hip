@@ -72,7 +72,7 @@ pic_status validate(const pic_config* c) {
   if (c->slab_primaries < 0) return fail(PIC_EINVAL, "slab_primaries must be >= 0");
   if (c->capacity_factor < 0 || !std::isfinite(c->capacity_factor))
     return fail(PIC_EINVAL, "capacity_factor must be >= 0");
-  uint64_t roots_end = 0;
+  std::vector<std::pair<uint64_t, uint64_t>> roots;  // [root_offset, + n_primaries) per instance
   for (int i = 0; i < c->n_instances; ++i) {
     const pic_instance& I = c->inst[i];
     const std::string w = "instance " + std::to_string(i) + ": ";
@@ -135,8 +135,14 @@ pic_status validate(const pic_config* c) {
     if (I.n_primaries < 0) return fail(PIC_EINVAL, w + "n_primaries < 0");
     if (I.root_offset + (uint64_t)I.n_primaries > 0x100000000ull)
       return fail(PIC_EINVAL, w + "root ids must fit in 32 bits");
-    roots_end = std::max(roots_end, I.root_offset + (uint64_t)I.n_primaries);
+    if (I.n_primaries > 0) roots.emplace_back(I.root_offset, I.root_offset + (uint64_t)I.n_primaries);
   }
+  // Root ids key the random streams of a primary tree (and its slot of per-tree returns in
+  // the adjoint): two instances sharing a root would replay each other's trees.
+  std::sort(roots.begin(), roots.end());
+  for (size_t k = 1; k < roots.size(); ++k)
+    if (roots[k].first < roots[k - 1].second)
+      return fail(PIC_EINVAL, "instances have overlapping root id ranges [root_offset, root_offset + n_primaries)");
   if (c->adjoint < 0 || c->adjoint > 3) return fail(PIC_EINVAL, "adjoint must be 0..3");
   if (c->adjoint) {
     const pic_instance& I0 = c->inst[0];

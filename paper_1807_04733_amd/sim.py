@@ -131,6 +131,7 @@ class PicSim:
         # a stream of our own (default priority): the legacy NULL stream cannot be
         # captured into a graph
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.handle = C.c_void_p()
         with torch.cuda.stream(self.stream):
             raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         shift = (-raw.data_ptr()) % 256
@@ -138,7 +139,6 @@ class PicSim:
             raise RuntimeError("workspace allocation is not 8-byte aligned")
         self._raw = raw
         self.ws = raw[shift:shift + self.ws_bytes]
-        self.handle = C.c_void_p()
         _abi.check(self.lib.pic_init(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()),
                                      C.c_int64(self.ws_bytes),
                                      C.c_void_p(self.stream.cuda_stream),
@@ -213,19 +213,25 @@ class PicSim:
                                for x in g])
             return torch.as_tensor(g, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
 
-        with torch.cuda.stream(self.stream):
-            gd = flat(g_dens)
-            gc = flat(g_cur)
-            if gd is not None and gd.numel() != self.layout.dens_len:
-                raise ValueError("g_dens does not match the density bins")
-            if gc is not None and gc.numel() != self.layout.cur_len:
-                raise ValueError("g_cur does not match the current bins")
-            grad = torch.zeros(self.n_params, dtype=torch.float64, device=self.device)
-            torch.cuda.current_stream(self.device).synchronize()
-            _abi.check(self.lib.pic_backward(
-                self.handle, C.c_void_p(gd.data_ptr() if gd is not None else 0),
-                C.c_void_p(gc.data_ptr() if gc is not None else 0),
-                C.c_void_p(grad.data_ptr()), int(estimator)))
+        # the loss weights are produced on the caller's stream (autograd's); the replay runs
+        # on the library's stream, which first waits for everything queued there
+        caller = torch.cuda.current_stream(self.device)
+        gd = flat(g_dens)
+        gc = flat(g_cur)
+        if gd is not None and gd.numel() != self.layout.dens_len:
+            raise ValueError("g_dens does not match the density bins")
+        if gc is not None and gc.numel() != self.layout.cur_len:
+            raise ValueError("g_cur does not match the current bins")
+        grad = torch.zeros(self.n_params, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(caller)
+        for t in (gd, gc, grad):
+            if t is not None:
+                t.record_stream(self.stream)
+        # pic_backward synchronizes the library stream before it returns
+        _abi.check(self.lib.pic_backward(
+            self.handle, C.c_void_p(gd.data_ptr() if gd is not None else 0),
+            C.c_void_p(gc.data_ptr() if gc is not None else 0),
+            C.c_void_p(grad.data_ptr()), int(estimator)))
         return grad.cpu().numpy()
 
     def counters(self) -> np.ndarray:
@@ -238,12 +244,17 @@ class PicSim:
         import torch
 
         lay = self.layout
-        with torch.cuda.stream(self.stream):
-            d = torch.empty(lay.dens_len, dtype=torch.float64, device=self.device)
-            c = torch.empty(lay.cur_len, dtype=torch.float64, device=self.device)
-            _abi.check(self.lib.pic_deposit(self.handle, C.c_void_p(d.data_ptr()),
-                                            C.c_void_p(c.data_ptr())))
-        self.stream.synchronize()
+        # outputs belong to the caller's stream: the conversion on the library stream waits
+        # for their allocation, and the caller's stream waits for the conversion
+        caller = torch.cuda.current_stream(self.device)
+        d = torch.empty(lay.dens_len, dtype=torch.float64, device=self.device)
+        c = torch.empty(lay.cur_len, dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(caller)
+        _abi.check(self.lib.pic_deposit(self.handle, C.c_void_p(d.data_ptr()),
+                                        C.c_void_p(c.data_ptr())))
+        d.record_stream(self.stream)
+        c.record_stream(self.stream)
+        caller.wait_stream(self.stream)
         dens, cur = [], []
         od = oc = 0
         for i in range(len(self.problem.instances)):
@@ -264,10 +275,12 @@ class PicSim:
 
         shapes = [self.problem.gen_shape(i) for i in range(len(self.problem.instances))]
         n = sum(int(np.prod(sh)) for sh in shapes)
-        with torch.cuda.stream(self.stream):
-            g = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
-            _abi.check(self.lib.pic_generations(self.handle, C.c_void_p(g.data_ptr())))
-        self.stream.synchronize()
+        caller = torch.cuda.current_stream(self.device)
+        g = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(caller)
+        _abi.check(self.lib.pic_generations(self.handle, C.c_void_p(g.data_ptr())))
+        g.record_stream(self.stream)
+        caller.wait_stream(self.stream)
         out, o = [], 0
         for sh in shapes:
             m = int(np.prod(sh))

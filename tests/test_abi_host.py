@@ -83,7 +83,7 @@ def test_workspace_size_grows_with_primaries(abi):
 
 @pytest.mark.parametrize("breaker", ["z_grid", "T_range", "dt", "tau_exp", "edges", "speed",
                                      "layers", "roots", "e_nodes", "e_scale", "v_node",
-                                     "r_node"])
+                                     "r_node", "root_overlap"])
 def test_invalid_configs_rejected(abi, breaker):
     prob = W.config0(n_primaries=100, n_steps=10)
     inst = prob.instances[0]
@@ -109,6 +109,10 @@ def test_invalid_configs_rejected(abi, breaker):
         inst.tt_of = np.zeros((16, 2, 2), np.int32)
     elif breaker == "roots":
         inst.root_offset = 2 ** 32 - 10
+    elif breaker == "root_overlap":
+        # a second instance whose root ids [50, 150) overlap the first's [0, 100)
+        from dataclasses import replace
+        prob.instances = [inst, replace(inst, root_offset=50)]
     elif breaker in ("e_nodes", "e_scale", "v_node", "r_node"):
         inst.v_tab, inst.r_tab, inst.e_scale = W.synthetic_channel_tables(inst.v)
         if breaker == "e_nodes":
@@ -125,3 +129,13 @@ def test_invalid_configs_rejected(abi, breaker):
         return  # rejected by the binding before reaching the library
     assert rc == 1
     assert abi.load().pic_last_error()
+
+
+def test_disjoint_root_ranges_accepted(abi):
+    """Instances whose root ranges touch but do not overlap, in any order, are valid."""
+    from dataclasses import replace
+    prob = W.config0(n_primaries=100, n_steps=10)
+    inst = prob.instances[0]
+    prob.instances = [replace(inst, root_offset=100), inst, replace(inst, root_offset=300)]
+    rc, n = _size(abi, prob)
+    assert rc == 0 and n > 0
