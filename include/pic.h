@@ -20,7 +20,8 @@
  * Memory and streams
  *   - The library never allocates device memory.  The caller supplies one device
  *     workspace of at least pic_workspace_size() bytes (256-byte aligned) and keeps it
- *     alive until pic_destroy().  Output arrays passed to pic_deposit() are caller-owned
+ *     alive until pic_destroy(), or sets up with pic_init_static(), which uses a static
+ *     array of the library instead.  Output arrays passed to pic_deposit() are caller-owned
  *     device memory.  All device work is enqueued on the HIP stream given to pic_init()
  *     (NULL = the default stream).  pic_init(), pic_inject(), pic_counters(),
  *     pic_backward(), pic_autotune(), pic_time_kernels(), pic_kernel_times() and
@@ -201,6 +202,25 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
 /* Set the source schedule, Eq. (17): sched[i*n_steps + n] primaries of instance i are
  * created at the start of step n (host array; each row must sum to n_primaries). */
 pic_status pic_inject(pic_ctx* ctx, const int64_t* sched);
+
+/* Bytes of the static workspace behind pic_init_static(), one array per device. */
+#define PIC_STATIC_WORKSPACE_BYTES (64ll << 20)
+
+/* Allocation-free set-up, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): pic_init() with
+ * the library's own static device array of PIC_STATIC_WORKSPACE_BYTES on the current
+ * device as the workspace, so that neither this call nor the context's later calls
+ * allocate device memory.  Every other call works on the context as on any other;
+ * pic_deposit() and pic_backward() still write to caller-owned device arrays.  The
+ * context launches its steps directly (pic_tuning.use_graph = 0; setting it to 1 makes
+ * pic_step() instantiate a graph, which may allocate).  Each device holds its array from
+ * the library's first use on that device until the process ends, and the array keeps the
+ * previous context's contents (the set-up clears what must start at zero).  One live
+ * context per device may own the array: a second call on the same device before
+ * pic_destroy() of the first returns PIC_ESTATE (two contexts sharing it would race).
+ * PIC_ENOMEM if the problem's workspace (pic_workspace_size) exceeds
+ * PIC_STATIC_WORKSPACE_BYTES.  `stream` must belong to the current device. */
+pic_status pic_init_static(const pic_config* cfg, void* stream, pic_ctx** out);
 
 /* Enqueue n steps (the next ones after those already run): one kernel launch per
  * pic_tuning.sub_steps steps. */

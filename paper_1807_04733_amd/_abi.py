@@ -23,11 +23,12 @@ F_WEIGHTS = 32
 COUNTER_NAMES = ("injected", "ev_ee", "ev_el", "spawned", "absorbed", "sec_absorbed",
                  "transmit", "refl_if", "refl_surf", "alive", "e_absorbed", "w_injected")
 NCOUNTERS = len(COUNTER_NAMES)
+STATIC_WORKSPACE_BYTES = 64 << 20   # PIC_STATIC_WORKSPACE_BYTES
 
 STATUS = {0: "PIC_OK", 1: "PIC_EINVAL", 2: "PIC_ENOMEM", 3: "PIC_ECAPACITY", 4: "PIC_EHIP",
           5: "PIC_ESTATE"}
 
-EXPORTS = ("pic_workspace_size", "pic_init", "pic_inject", "pic_step", "pic_compact", "pic_deposit",
+EXPORTS = ("pic_workspace_size", "pic_init", "pic_init_static", "pic_inject", "pic_step", "pic_compact", "pic_deposit",
            "pic_backward", "pic_counters", "pic_reset", "pic_set_tuning", "pic_get_tuning",
            "pic_layout_of", "pic_autotune", "pic_time_kernels", "pic_kernel_times",
            "pic_generations",
@@ -110,6 +111,7 @@ def load():
     sig = {
         "pic_workspace_size": ([P(PicConfig), P(C.c_int64)], C.c_int),
         "pic_init": ([P(PicConfig), vp, C.c_int64, vp, P(vp)], C.c_int),
+        "pic_init_static": ([P(PicConfig), vp, P(vp)], C.c_int),
         "pic_inject": ([vp, P(C.c_int64)], C.c_int),
         "pic_step": ([vp, C.c_int32], C.c_int),
         "pic_compact": ([vp], C.c_int),

@@ -288,6 +288,7 @@ Plan make_plan(const pic_config* c) {
 }  // namespace
 
 struct pic_ctx {
+  int static_dev = -1;         // >= 0: the workspace is that device's static array
   pic_config cfg;
   std::vector<pic_instance> inst;
   Plan plan;
@@ -699,7 +700,16 @@ pic_status pic_workspace_size(const pic_config* cfg, int64_t* bytes) {
   return PIC_OK;
 }
 
-pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_bytes, void* stream,
+}  // extern "C"
+
+// Workspace of the allocation-free set-up: one array per device, held by the process from
+// the library's load on that device until it ends.  Host code never uses the array's name
+// as an address: each device's copy is resolved once with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[PIC_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+pic_status init_ctx(const pic_config* cfg, void* workspace, int64_t workspace_bytes, void* stream,
                     pic_ctx** out) {
   pic_status st = validate(cfg);
   if (st != PIC_OK) return st;
@@ -747,6 +757,52 @@ pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_by
     delete c;
     return st;
   }
+  *out = c;
+  return PIC_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices];             // device address of `scratch`, per device
+const pic_ctx* g_static_owner[kMaxDevices];  // the live context using it, per device
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_bytes, void* stream,
+                    pic_ctx** out) {
+  return init_ctx(cfg, workspace, workspace_bytes, stream, out);
+}
+
+pic_status pic_init_static(const pic_config* cfg, void* stream, pic_ctx** out) {
+  pic_status st = validate(cfg);
+  if (st != PIC_OK) return st;
+  if (!out) return fail(PIC_EINVAL, "null output");
+  const int64_t need = make_plan(cfg).bytes;
+  if (need > (int64_t)PIC_STATIC_WORKSPACE_BYTES)
+    return fail(PIC_ENOMEM, "problem needs a workspace of " + std::to_string(need) +
+                                " bytes, more than the static workspace of " +
+                                std::to_string((int64_t)PIC_STATIC_WORKSPACE_BYTES) + " bytes");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PIC_EINVAL, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255)) return fail(PIC_EHIP, "static workspace address unusable");
+    g_static_ptr[dev] = p;
+  }
+  if (g_static_owner[dev])
+    return fail(PIC_ESTATE, "the static workspace of this device belongs to a live context "
+                            "(pic_destroy it first)");
+  pic_ctx* c = nullptr;
+  st = init_ctx(cfg, g_static_ptr[dev], (int64_t)PIC_STATIC_WORKSPACE_BYTES, stream, &c);
+  if (st != PIC_OK) return st;
+  c->static_dev = dev;
+  c->tune.use_graph = 0;  // instantiating a graph may allocate; steps launch directly
+  g_static_owner[dev] = c;
   *out = c;
   return PIC_OK;
 }
@@ -1043,9 +1099,11 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      pic_status st = pic_set_tuning(c, &it->second);
+      pic_tuning t = it->second;
+      if (c->static_dev >= 0) t.use_graph = 0;
+      pic_status st = pic_set_tuning(c, &t);
       if (st != PIC_OK) return st;
-      if (best) *best = it->second;
+      if (best) *best = t;
       return clear_state(c);
     }
   }
@@ -1116,6 +1174,7 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune_cache[key] = win;
   }
+  if (c->static_dev >= 0) win.use_graph = 0;  // allocation-free contexts launch directly
   pic_status st = pic_set_tuning(c, &win);
   if (st != PIC_OK) return st;
   if (best) *best = win;
@@ -1169,6 +1228,10 @@ void pic_destroy(pic_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   drop_events(c);
+  if (c->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_owner[c->static_dev] == c) g_static_owner[c->static_dev] = nullptr;
+  }
   delete c;
 }
 

@@ -116,7 +116,12 @@ class PicSim:
 
     def __init__(self, problem, *, device="cuda", debug: bool = False,
                  slab_primaries: int = 0, capacity_factor: float = 0.0, stream=None,
-                 tuning: Optional[dict] = None, adjoint: int = 0):
+                 tuning: Optional[dict] = None, adjoint: int = 0,
+                 static_workspace: bool = False):
+        """static_workspace=True sets up with pic_init_static (the library's own device
+        array, no allocation; one such context per device at a time); the inspection
+        helpers that read the workspace (int_bins, particles, alive_energy) are then not
+        available."""
         import torch
 
         self.problem = problem
@@ -132,17 +137,24 @@ class PicSim:
         # captured into a graph
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.handle = C.c_void_p()
-        with torch.cuda.stream(self.stream):
-            raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-        shift = (-raw.data_ptr()) % 256
-        if shift % 8:
-            raise RuntimeError("workspace allocation is not 8-byte aligned")
-        self._raw = raw
-        self.ws = raw[shift:shift + self.ws_bytes]
-        _abi.check(self.lib.pic_init(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()),
-                                     C.c_int64(self.ws_bytes),
-                                     C.c_void_p(self.stream.cuda_stream),
-                                     C.byref(self.handle)))
+        if static_workspace:
+            self._raw = self.ws = None
+            with torch.cuda.device(self.device):
+                _abi.check(self.lib.pic_init_static(C.byref(self._cfg),
+                                                    C.c_void_p(self.stream.cuda_stream),
+                                                    C.byref(self.handle)))
+        else:
+            with torch.cuda.stream(self.stream):
+                raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            shift = (-raw.data_ptr()) % 256
+            if shift % 8:
+                raise RuntimeError("workspace allocation is not 8-byte aligned")
+            self._raw = raw
+            self.ws = raw[shift:shift + self.ws_bytes]
+            _abi.check(self.lib.pic_init(C.byref(self._cfg), C.c_void_p(self.ws.data_ptr()),
+                                         C.c_int64(self.ws_bytes),
+                                         C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(self.handle)))
         sched = np.ascontiguousarray(np.stack([it.sched for it in problem.instances]), np.int64)
         _abi.check(self.lib.pic_inject(self.handle, sched.ctypes.data_as(C.POINTER(C.c_int64))))
         self.layout = _abi.PicLayout()
@@ -292,6 +304,7 @@ class PicSim:
         """The raw integer bins (uint64 counts, int64 2^-32 nm/fs) as host arrays."""
         import torch
 
+        self._need_ws()
         self.stream.synchronize()
         lay = self.layout
         d = self.ws[lay.off_dens:lay.off_dens + 8 * lay.dens_len].view(torch.int64)
@@ -316,6 +329,7 @@ class PicSim:
         (selected on the device, so that full-size runs can be sampled)."""
         import torch
 
+        self._need_ws()
         self.stream.synchronize()
         lay = self.layout
         ws = self.ws
@@ -373,6 +387,7 @@ class PicSim:
         """Sum of the fixed-point energies of all live carriers (inspection helper)."""
         import torch
 
+        self._need_ws()
         self.stream.synchronize()
         lay = self.layout
         with torch.cuda.stream(self.stream):
@@ -388,6 +403,10 @@ class PicSim:
             tot = (E[ti].to(torch.int64) & 0xFFFFFFFF)[live].sum()
         self.stream.synchronize()
         return int(tot.item())
+
+    def _need_ws(self):
+        if self.ws is None:
+            raise RuntimeError("a context on the static workspace has no workspace tensor")
 
     def close(self):
         if self.handle:
