@@ -194,8 +194,12 @@ typedef struct pic_ctx pic_ctx;
 /* Bytes of device workspace a context for `cfg` needs.  PIC_EINVAL on a bad config. */
 pic_status pic_workspace_size(const pic_config* cfg, int64_t* bytes);
 
-/* Validate `cfg`, lay out the workspace, upload the tables and clear the state.
- * `stream` is a hipStream_t (or NULL).  Enqueues work; does not synchronize. */
+/* Set up one simulation of the 1-D hot-electron Boltzmann equation, Eq. (9), by the
+ * particle-in-cell method of Sec. III.A for the layer stacks and parameters in `cfg`
+ * (Eqs. 2, 7, 8, 19): validate `cfg` (PIC_EINVAL), lay out the caller's workspace
+ * (PIC_ENOMEM if smaller than pic_workspace_size()), upload the tables and clear the
+ * particles, bins and counters.  `stream` is a hipStream_t (or NULL).  The context is
+ * host memory owned by the library until pic_destroy(). */
 pic_status pic_init(const pic_config* cfg, void* workspace, int64_t workspace_bytes,
                     void* stream, pic_ctx** out);
 
@@ -222,8 +226,15 @@ pic_status pic_inject(pic_ctx* ctx, const int64_t* sched);
  * PIC_STATIC_WORKSPACE_BYTES.  `stream` must belong to the current device. */
 pic_status pic_init_static(const pic_config* cfg, void* stream, pic_ctx** out);
 
-/* Enqueue n steps (the next ones after those already run): one kernel launch per
- * pic_tuning.sub_steps steps. */
+/* Enqueue n time steps (the next ones after those already run).  One step is the Strang
+ * splitting of Eq. (15) for every superparticle of every instance: Source(dt/2) (the
+ * primaries of the schedule, Eq. 17), Transport(dt/2) (Eq. 18 with vacuum reflection and
+ * the stochastic interfaces of Sec. III.A), Scattering(dt) (one Monte-Carlo event with
+ * p = 1 - exp(-dt/tau_eff), Eq. 2: elastic, Eq. 8, or inelastic with a secondary, Eqs. 6,
+ * 7, 19; products below E_min removed), Transport(dt/2), then the moments of Eqs. (16)
+ * and (23) added to the integer bins of the step.  One kernel launch per
+ * pic_tuning.sub_steps steps.  PIC_EINVAL if the steps would go beyond n_steps,
+ * PIC_ESTATE before pic_inject().  Device conditions are reported by pic_counters(). */
 pic_status pic_step(pic_ctx* ctx, int32_t n);
 
 /* Enqueue one compaction pass now (slabs whose dead slots exceed
@@ -231,9 +242,12 @@ pic_status pic_step(pic_ctx* ctx, int32_t n);
  * runs it every compact_every steps; this entry lets a caller time it separately. */
 pic_status pic_compact(pic_ctx* ctx);
 
-/* Convert the integer bins to binary64: dens_out [sum_i n_dslots*nz_i*NE*2] particle
- * counts and cur_out [sum_i n_cslots*nz_i*2] sum of v*cos(theta) in nm/fs; instances are
- * concatenated in order.  With PIC_F_WEIGHTS both are weighted sums (the integer density
+/* The moments of the run so far as binary64: the density of Eq. (16) (carriers per depth
+ * bin, energy bin and spin) and the spin-resolved current moment of Eq. (23) (sum of
+ * v cos(theta) per depth bin and spin; j_s is the up minus the down column, units
+ * dropped as in the paper).  Converts the integer bins: dens_out
+ * [sum_i n_dslots*nz_i*NE*2] particle counts and cur_out [sum_i n_cslots*nz_i*2] in
+ * nm/fs; instances are concatenated in order.  With PIC_F_WEIGHTS both are weighted sums (the integer density
  * bins hold weights in 2^-16 units, the current bins rint(v cos(theta) w 2^32) per
  * carrier).  Device pointers (either may be NULL).  Enqueued, async. */
 pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
@@ -247,8 +261,11 @@ pic_status pic_deposit(pic_ctx* ctx, double* dens_out, double* cur_out);
  * Enqueued, async.  PIC_ESTATE without the flag. */
 pic_status pic_generations(pic_ctx* ctx, double* gen_out);
 
-/* Likelihood-ratio adjoint: gradient of sum(g_dens*dens) + sum(g_cur*cur) with respect
- * to ln tau0 per channel and every transmission-table entry, written to grad_out
+/* Likelihood-ratio adjoint of the run (score-function estimator over the Monte-Carlo
+ * decisions of Sec. III.A: the event probability of Eq. 2, the channel choice of Eqs. 5
+ * and 8, the interface transmissions): gradient of sum(g_dens*dens) + sum(g_cur*cur)
+ * with respect to ln tau0 per channel and every transmission-table entry, written to
+ * grad_out
  * (device, [n_channels + n_ttables*t_entries], summed over instances).  Replays the run
  * from step 0 with the same random streams (the particle state is rebuilt; bins are
  * untouched).  estimator 0: causal score carried by each carrier (needs K <= 16 and

@@ -357,18 +357,28 @@ size_t lds_per_cu() {
   return cached;
 }
 
+// LDS one workgroup of `block` threads may use without lowering the number of its
+// workgroups per CU below the register limit (at most 16 waves of the step kernel per CU).
+size_t lds_per_wg(int block) {
+  return lds_per_cu() / (size_t)std::max(1, 16 / (block / 64));
+}
+
 // Dynamic LDS layout of one step launch over n_sub sub-steps: the density slices (of the
 // sub-steps that deposit density, when density goes to LDS), the current slices, the
 // per-wave queues, then (where they fit) the per-wave copies of the sub-step-0 queue's
 // carrier state.  Fills the offsets in `a` (if given) and returns the bytes.
 size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, const int* cur_on,
-                   StepArgs* a) {
+                   StepArgs* a, bool dens16 = false) {
   size_t off = 0;
+  // a density slice: u64 weight sums, u32 counts, or 16-bit counts packed two per word
+  const size_t dens_bytes = dens16 ? (size_t)c->lds_dens_words * 2
+                                   : (size_t)c->lds_dens_words * dens_elem(c);
   for (int j = 0; j < kMaxSub; ++j) {
     const bool d = j < n_sub && dens_on[j] && c->dens_lds;
     if (a) a->lds_dens_at[j] = d ? (int32_t)off : -1;
-    if (d) off = (off + (size_t)c->lds_dens_words * dens_elem(c) + 15) & ~(size_t)15;
+    if (d) off = (off + dens_bytes + 15) & ~(size_t)15;
   }
+  if (a) a->dens16 = dens16 ? 1 : 0;
   for (int j = 0; j < kMaxSub; ++j) {
     const bool u = j < n_sub && cur_on[j];
     if (a) a->lds_cur_at[j] = u ? (int32_t)off : -1;
@@ -393,7 +403,7 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
   const size_t stage_at = (off + 15) & ~(size_t)15;
   const size_t stage_end =
       stage_at + (size_t)(block / 64) * stage_wave_bytes(c->plan.state_bytes == 8);
-  const size_t per_wg = lds_per_cu() / (size_t)std::max(1, 16 / (block / 64));
+  const size_t per_wg = lds_per_wg(block);
   const size_t stat = step_static_lds();
   const bool stage = stage_end + stat <= per_wg && stage_end <= c->max_lds;
   if (a) a->lds_stage_at = stage ? (int32_t)stage_at : -1;
@@ -524,13 +534,23 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
       dens_on[j] = j < ns && (sj % c->cfg.dens_stride) == 0;
       cur_on[j] = j < ns && (sj % c->cfg.cur_stride) == 0;
     }
+    // Two density slices of 32-bit counters that would cost a workgroup per CU are held as
+    // 16-bit counters (unweighted runs without energy tables; the counts stay exact).
+    bool dens16 = false;
+    if (ns > 1 && dens_on[0] && dens_on[1] && c->dens_lds && c->plan.off_w < 0 &&
+        c->plan.etab_max == 0 &&
+        step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) + step_static_lds() >
+            lds_per_wg(c->tune.block))
+      dens16 = true;
     // one step at a time where two density slices do not fit next to each other, or where
     // the first step would have to store z
     const bool first_writes = (s - start) % K == K - 1 || s == start + n - 1;
     if (ns > 1 && (first_writes ||
-                   step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) > c->max_lds)) {
+                   step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr, dens16) >
+                       c->max_lds)) {
       ns = 1;
       dens_on[1] = cur_on[1] = 0;
+      dens16 = false;
     }
     a.n_sub = ns;
     for (int j = 0; j < kMaxSub; ++j) {
@@ -548,7 +568,7 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
     std::memset(&L, 0, sizeof(L));
     L.grid = grid;
     L.block = c->tune.block;
-    L.lds = step_layout(c, c->tune.block, ns, dens_on, cur_on, &a);
+    L.lds = step_layout(c, c->tune.block, ns, dens_on, cur_on, &a, dens16);
     hipEvent_t* ev = nullptr;
     if (c->timing) {
       c->tev.emplace_back();

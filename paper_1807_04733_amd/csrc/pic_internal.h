@@ -106,7 +106,9 @@ struct StepArgs {
   int32_t dens_on, cur_on;     // this step deposits density / current
   int32_t dens_slot, cur_slot;
   int32_t dens_lds;            // density privatised in LDS (else global atomics)
-  int32_t lds_dens_words;      // u32 words of the LDS density histogram
+  int32_t lds_dens_words;      // bins of the LDS density histogram
+  int32_t dens16;              // LDS density slices hold 16-bit counters, two per word
+                               // (unweighted runs without energy tables)
   int32_t lds_cur_words;       // u64 words of the LDS current histogram
   int32_t inst_bytes;          // bytes of DevInst copied into LDS
   // Write-back schedule of z on the common path: the stored z of a carrier is its

@@ -36,6 +36,7 @@ constexpr int kModeDebug = 1;       // keep per-particle event counts
 constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slice does not fit)
 constexpr int kModeTab = 8;         // energy-dependent speeds and rates (tables in LDS)
 constexpr int kModeWt = 16;         // weighted superparticles (StepArgs::wt)
+constexpr int kModeDens16 = 32;     // density slices as 16-bit counters, two per LDS word
 
 // Compile-time sub-step index for the generic lambdas of k_step.
 template <int V>
@@ -47,6 +48,25 @@ struct Sub {
 template <int MODE>
 __device__ __forceinline__ bool weighted(const StepArgs& a) {
   return (MODE & kModeWt) != 0;
+}
+
+// A 16-bit density counter of the LDS slice wrapped (rare: 65536 deposits into one bin of
+// one workgroup's slice).  The 32-bit word holds bin 2k in its low and bin 2k+1 in its high
+// half and only ever receives additions, so every wrap of a half is seen by exactly the
+// atomic that causes it (from the value it returns): that lane moves 65536 into the
+// int64 bin, and a carry out of the low half into the high half is taken back out at once
+// (a wrap of the high half caused by the carry or by taking it back out is counted the
+// same way).  The slice then holds every bin's count modulo 65536 and the int64 bins the
+// rest, exactly, whatever the order of the concurrent additions.
+__device__ __forceinline__ void dens16_wrap(unsigned long long* g, int idx, uint32_t sh,
+                                            uint32_t old, uint32_t* wd) {
+  atomicAdd(&g[idx], 65536ull);
+  if (sh == 0) {
+    const int hi_bin = idx + 1;
+    if ((old >> 16) == 0xFFFFu) atomicAdd(&g[hi_bin], 65536ull);
+    const uint32_t old2 = atomicAdd(wd, 0xFFFF0000u);
+    if ((old2 >> 16) == 0u) atomicAdd(&g[hi_bin], (unsigned long long)(-65536ll));
+  }
 }
 
 // Deposit of one carrier at the end of sub-step J into the LDS histogram slices of that
@@ -67,6 +87,14 @@ __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, u
     if (MODE & kModeDensGlobal) {
       const int64_t g = I.dens_off + (int64_t)a.sub_dens_slot[J] * I.nz * a.n_ebins * 2 + idx;
       atomicAdd((unsigned long long*)&a.dens[g], add);
+    } else if (MODE & kModeDens16) {
+      uint32_t* wd = (uint32_t*)(dyn + a.lds_dens_at[J]) + (idx >> 1);
+      const uint32_t sh = (uint32_t)(idx & 1) << 4;
+      const uint32_t old = atomicAdd(wd, 1u << sh);
+      if (__builtin_expect(((old >> sh) & 0xFFFFu) == 0xFFFFu, 0))
+        dens16_wrap((unsigned long long*)(a.dens + I.dens_off +
+                                          (int64_t)a.sub_dens_slot[J] * I.nz * a.n_ebins * 2),
+                    idx, sh, old, wd);
     } else if (wtd) {
       atomicAdd((unsigned long long*)(dyn + a.lds_dens_at[J]) + idx, add);
     } else {
@@ -124,6 +152,18 @@ __device__ __forceinline__ void merge_slice(U* s, unsigned long long* g, int n) 
   }
 }
 
+// The same for a slice of n 16-bit counters packed two per 32-bit word (n even).
+__device__ __forceinline__ void merge_slice16(uint32_t* s, unsigned long long* g, int n) {
+  for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+    const uint32_t v = s[b];
+    if (v) {
+      if (v & 0xFFFFu) atomicAdd(&g[2 * b], (unsigned long long)(v & 0xFFFFu));
+      if (v >> 16) atomicAdd(&g[2 * b + 1], (unsigned long long)(v >> 16));
+      s[b] = 0;
+    }
+  }
+}
+
 // Merge sub-step J's LDS histogram slices of the workgroup's instance into the int64 bins
 // and clear them.
 template <int MODE, int J>
@@ -134,6 +174,7 @@ __device__ void flush_bins(const StepArgs& a, const DevInst& I, unsigned char* d
     unsigned long long* g =
         (unsigned long long*)(a.dens + I.dens_off + (int64_t)a.sub_dens_slot[J] * n);
     if (wtd) merge_slice((unsigned long long*)(dyn + a.lds_dens_at[J]), g, n);
+    else if (MODE & kModeDens16) merge_slice16((uint32_t*)(dyn + a.lds_dens_at[J]), g, n);
     else merge_slice((uint32_t*)(dyn + a.lds_dens_at[J]), g, n);
     if (a.gen) {
       const int m = I.nz * 2;
@@ -546,7 +587,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         if (dirty & 4u) at(sp.fl, gi) = fl;
         if (DEBUG) at(sp.ev, gi) = evp;
       }
-      const uint64_t md = __ballot(died);
+      // the slab's dead count: carriers that died in a slot of the slab (a new primary that
+      // found no free slot is not one), so that tail - dead is the live count
+      const uint64_t md = __ballot(died && placed);
       if (md && lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&s_dead, __popcll(md));
       return alive0 && !died && placed;
     };
@@ -891,11 +934,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
 // In-place compaction of slabs whose tombstones exceed a fraction of their tail.  With L
 // live carriers in a slab, the live carriers at or above slot L move into the dead slots
 // below L and the tail becomes L, so about as many carriers move as there are tombstones
-// below L (the order of carriers in a slab changes no result).  One workgroup per slab
-// counts the live carriers, then collects dead slots below L and live slots at or above L
-// into two LDS rings, kScanTile slots per scan round, and moves them in pairs.  Sources
-// and destinations lie on either side of L, so the moves need no ordering among
-// themselves; the two counts are equal, so every dead slot below L is filled.
+// below L (the order of carriers in a slab changes no result).  L is the tail minus the
+// slab's dead count, which the step kernels keep exact.  One workgroup per slab collects
+// dead slots below L and live slots at or above L into two LDS rings, kScanTile slots per
+// scan round, and moves them in pairs.  Sources and destinations lie on either side of L,
+// so the moves need no ordering among themselves; the two counts are equal, so every dead
+// slot below L is filled.
 constexpr int kCompactBlock = 256;
 constexpr int kCompactPer = 4;                                // slots per thread per round
 constexpr int kScanTile = kCompactBlock * kCompactPer;
@@ -908,7 +952,7 @@ static_assert(kHoleBatch - 1 + kScanTile <= kRingH && kRingH - 1 + kScanTile <= 
 template <typename F>
 __global__ void __launch_bounds__(kCompactBlock) k_compact(CompactArgs a) {
   __shared__ int sH[kRingH], sT[kRingT];
-  __shared__ int s_cnt[3];  // appended dead slots, appended live slots, live carriers
+  __shared__ int s_cnt[2];  // appended dead slots, appended live slots
   const int slab = blockIdx.x;
   const int tail = a.slab_tail[slab];
   const int dead = a.slab_dead[slab];
@@ -916,24 +960,10 @@ __global__ void __launch_bounds__(kCompactBlock) k_compact(CompactArgs a) {
   const int64_t base = a.slab_base[slab];
   const uint32_t* const fl = a.flags + base;
   const int tid = threadIdx.x, lane = __lane_id();
-  if (tid < 3) s_cnt[tid] = 0;
+  if (dead > tail) return;  // never happens: the step kernels count only dead slots
+  if (tid < 2) s_cnt[tid] = 0;
   __syncthreads();
-  {
-    int live = 0;
-    for (int tb = 0; tb < tail; tb += kScanTile) {
-      uint32_t f[kCompactPer];
-#pragma unroll
-      for (int j = 0; j < kCompactPer; ++j) {
-        const int t = tb + j * kCompactBlock + tid;
-        f[j] = t < tail ? fl[t] : kDead;
-      }
-#pragma unroll
-      for (int j = 0; j < kCompactPer; ++j) live += (f[j] & kDead) ? 0 : 1;
-    }
-    if (live) atomicAdd(&s_cnt[2], live);
-  }
-  __syncthreads();
-  const int L = s_cnt[2];
+  const int L = tail - dead;
   // wave-aggregated append of slot t to a ring (absolute positions; index = position & mask)
   auto append = [&](bool want, int t, int* ring, int mask, int* ctr) {
     const uint64_t m = __ballot(want);
@@ -1027,7 +1057,7 @@ static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
 
 // the launch modes that are instantiated: debug x density placement x tables x weights
 using StepModes = std::integer_sequence<int, 0, 1, 4, 5, 8, 9, 12, 13, 16, 17, 20, 21, 24, 25,
-                                        28, 29>;
+                                        28, 29, 32, 33>;
 
 template <typename F, int T, int... Ms>
 static hipError_t launch_any(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s,
@@ -1072,7 +1102,8 @@ hipError_t set_step_lds_limit(size_t bytes) {
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
   const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
-                   (a.etab_words > 0 ? kModeTab : 0) | (a.wt ? kModeWt : 0);
+                   (a.etab_words > 0 ? kModeTab : 0) | (a.wt ? kModeWt : 0) |
+                   (dens_any && a.dens16 ? kModeDens16 : 0);
   if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
   hipError_t e;
   if (a.n_sub == 2)

@@ -612,3 +612,16 @@ def test_spin_importance_sampling_is_unbiased(oracle_lib):
     assert np.all(np.abs(diff) < 4 * se + 1e-9), (diff, se)
     # the sampling really differs: the unweighted count of spin-up carriers moves with q
     assert b[:, 0].mean() != a[:, 0].mean()
+
+
+def test_more_than_eight_hits_is_an_error(oracle_lib):
+    """Sixteen Au layers of 1/16 nm joined by T = 1 and half steps of up to 1 nm: a carrier
+    that would meet more than 8 boundaries in one half step makes the run fail (the limit
+    of the transport loop), while half steps shorter than a layer run clean."""
+    layers = [W.Layer("Au", 1.0 / 16) for _ in range(16)]
+    inst = W.make_instance(layers, n_primaries=256, n_steps=3, src_lambda=0.0,
+                           tau0=(INF, INF, INF, INF))
+    with pytest.raises(RuntimeError):
+        _run(oracle_lib, W.Problem([inst], seed=1, dt=2.0, n_steps=3, state_fp64=True))
+    res = _run(oracle_lib, W.Problem([inst], seed=1, dt=0.1, n_steps=3, state_fp64=True))
+    assert res.counters[:, oracle_lib.COUNTER_NAMES.index("transmit")].sum() > 0
