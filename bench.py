@@ -27,6 +27,10 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing one wave64 VALU instruction per 4
+# cycles (16 lanes per cycle; binary64 add/mul/fma and the 32x32->64 integer products run
+# at this full rate on gfx950), at 2.4 GHz: 6.144e11 wave instructions per second.
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 METRIC = "particle-steps/s (batched fwd, fwd+adjoint) & %HBM roofline at oracle tol"
 
 
@@ -125,6 +129,16 @@ def kernel_timing(sim):
     return rows, cnt
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, roots: int):
     import oracle
 
@@ -136,6 +150,7 @@ def cpu_baseline(prob, roots: int):
     ps = particle_steps(res.counters)
     n_roots = sum(min(roots, it.n_primaries) for it in prob.instances)
     return dict(value=ps / dt, unit="particle-steps/s", cores=threads, kind="oracle",
+                cpu=cpu_model(),
                 sample=f"first {roots} primaries of every instance ({n_roots} primary trees, "
                        f"{ps} particle-steps, {dt:.1f} s wall)")
 
@@ -185,8 +200,59 @@ def adjoint_leg(n_primaries: int, tune_steps: int):
                 tuning=tuning, grad=[float(x) for x in grad])
 
 
-def sequential_leg(prob, batched_s: float):
-    """The same stacks run one after another, one context and one graph each."""
+def multilayer_adjoint_leg(n_instances: int, tune_steps: int):
+    """[Fe(10)/Au(30)]x5 multilayers, a 50 fs Gaussian pump (3.125e6 primaries per stack),
+    T(E) tables of 64 nodes, 2000 x 0.5 fs: the forward run and its whole-tree adjoint over
+    260 parameters (ln tau0 of 4 channels, 4 tables x 64 nodes).  Loss: L2 distance of the
+    spin current over every (t, z) to a target curve (0.9 times the run's own).  By default
+    8 stacks, one GPU's share of the 64-stack workload sharded over 8 GPUs by stack."""
+    import torch
+    from paper_1807_04733_amd import PicSim
+
+    prob = W.config4(n_instances=n_instances)
+    sim = PicSim(prob, device="cuda:0", adjoint=2)
+    if tune_steps > 0:
+        # the pump peaks at step 200: tune on a prefix that holds most of it
+        sim.autotune(trial_steps=max(tune_steps, 250))
+    sim.step()
+    sim.counters()
+    sim.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step()
+    cnt = sim.counters()
+    t_fwd = time.perf_counter() - t0
+    d, c = sim.deposit()
+    g_cur = []
+    for ci in c:
+        js = ci[:, :, 0] - ci[:, :, 1]
+        g = torch.zeros_like(ci)
+        g[:, :, 0] = 2 * (js - 0.9 * js)
+        g[:, :, 1] = -2 * (js - 0.9 * js)
+        g_cur.append(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad = sim.backward(None, g_cur, 1)
+    t_bwd = time.perf_counter() - t0
+    ps = particle_steps(cnt)
+    tuning = sim.tuning()
+    sim.close()
+    del d, c, g_cur
+    torch.cuda.empty_cache()
+    return dict(workload=f"{n_instances} x [Fe(10)/Au(30)]x5, {prob.n_primaries:.3g} primaries "
+                         "(50 fs Gaussian pump), T(E) tables of 64 nodes, 2000 x 0.5 fs, FP32 "
+                         "state, L2 loss on the spin current, 260 parameters",
+                particle_steps=ps, forward_s=round(t_fwd, 4), adjoint_s=round(t_bwd, 4),
+                adjoint_over_forward=round(t_bwd / t_fwd, 3),
+                fwd_plus_adjoint_particle_steps_per_s=2 * ps / (t_fwd + t_bwd),
+                estimator="whole-tree return, two replays", tuning=tuning,
+                grad_norm=float(np.linalg.norm(grad)))
+
+
+def sequential_leg(prob, batched_s: float, tuning: dict):
+    """The same stacks run one after another, one context and one graph each, with the
+    batched run's launch tuning (workgroup size, grid, steps per launch, write-back and
+    compaction cadence), so that only the batching differs."""
     import torch
     from dataclasses import replace as dc_replace
     from paper_1807_04733_amd import PicSim
@@ -195,7 +261,7 @@ def sequential_leg(prob, batched_s: float):
     ps = 0
     for inst in prob.instances:
         one = dc_replace(prob, instances=[inst])
-        sim = PicSim(one, device="cuda:0")
+        sim = PicSim(one, device="cuda:0", tuning=tuning)
         sim.step()
         sim.counters()
         sim.reset()
@@ -209,7 +275,7 @@ def sequential_leg(prob, batched_s: float):
     torch.cuda.empty_cache()
     return dict(instances=len(prob.instances), sequential_s=round(total, 4),
                 batched_s=round(batched_s, 4), batched_speedup=round(total / batched_s, 3),
-                particle_steps=ps)
+                particle_steps=ps, tuning="the batched run's")
 
 
 def variants_leg(prob, tuning: dict):
@@ -274,6 +340,7 @@ KERNEL_SOURCES = ("paper_1807_04733_amd/csrc/pic_kernels.hip",
                   "paper_1807_04733_amd/csrc/pic_device.h",
                   "paper_1807_04733_amd/csrc/pic_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_hbm_traffic.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_sq_counters.md")
 
 
 def kernel_source_hash() -> str:
@@ -291,22 +358,38 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (otherwise None)."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_line(path: str, tag: str):
+    """The key=value pairs of the machine-readable `tag:` line of a committed profile
+    summary, if it was taken on the current kernel source (otherwise None)."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
-        if line.startswith("traffic:"):
+    for line in open(path):
+        if line.startswith(tag + ":"):
             for kv in line.split()[1:]:
                 k, v = kv.split("=")
                 vals[k] = v
     if vals.get("kernel_source") != kernel_source_hash():
         return None
+    return vals
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (otherwise None)."""
+    vals = _profile_line(TRAFFIC_FILE, "traffic")
+    if vals is None:
+        return None
     fetch = float(vals["fetch_kib"]) * float(vals["fetch_scale"]) * 1024
     write = float(vals["write_kib"]) * float(vals["write_scale"]) * 1024
     return fetch + write
+
+
+def measured_valu():
+    """VALU wave instructions per step launch (SQ_INSTS_VALU) from the committed counter
+    summary, if it was taken on the current kernel source (otherwise None)."""
+    vals = _profile_line(SQ_FILE, "valu")
+    return None if vals is None else float(vals["insts_per_launch"])
 
 
 def summarize_pmc(path: str, last: int):
@@ -354,6 +437,11 @@ def main():
                     help="run only a plain 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--adjoint-primaries", type=int, default=100_000_000,
                     help="primaries of the forward+adjoint leg (0: skip)")
+    ap.add_argument("--multilayer-instances", type=int, default=8,
+                    help="stacks of the multilayer forward + whole-tree adjoint leg (0: skip; "
+                         "64: the whole workload)")
+    ap.add_argument("--multilayer-only", action="store_true",
+                    help="run only the multilayer forward + adjoint leg and print it")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip running the batched stacks one by one")
     ap.add_argument("--no-variants", action="store_true",
@@ -388,6 +476,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4}))
+        return
+    if args.multilayer_only:
+        print(json.dumps(multilayer_adjoint_leg(args.multilayer_instances, args.tune_steps)))
         return
     if args.gpus != 1:
         print("this build runs on one GPU only: the particle update is sharded across GPUs "
@@ -447,9 +538,38 @@ def main():
         achieved = mb.sum() / (ms.sum() * 1e-3) / 1e9
         moved = b.sum() / (ms.sum() * 1e-3) / 1e9
         traffic = measured_traffic() if args.workload == "batched" else None
-        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=None if traffic is None else round(traffic, 0))
+        valu = measured_valu() if args.workload == "batched" else None
+        launch_s = float(ms.mean()) * 1e-3
+        # Two roofs for the step kernel.  HBM: the method's bytes per particle-step (the
+        # algorithmic bytes) over the launch time -- an effective rate, since the two-step
+        # kernel moves fewer bytes -- and beside it the measured traffic (rocprofv3
+        # FETCH_SIZE + WRITE_SIZE per launch) as a fraction of the peak.  VALU: the wave
+        # instructions per launch (SQ_INSTS_VALU) at the issue ceiling.  `bound` is the
+        # nearer roof by measurement (measured traffic vs VALU), and the top-level
+        # achieved / peak / frac are that roof's.
+        hbm = dict(achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(achieved / HBM_PEAK_GBS, 4),
+                   basis="method bytes per particle-step / launch time (effective)",
+                   traffic_gbs=None, traffic_frac=None)
+        if traffic is not None:
+            tg = traffic / launch_s / 1e9
+            hbm["traffic_gbs"] = round(tg, 1)
+            hbm["traffic_frac"] = round(tg / HBM_PEAK_GBS, 4)
+        valu_roof = None
+        if valu is not None:
+            vg = valu / launch_s / 1e9
+            valu_roof = dict(achieved=round(vg, 1), peak=VALU_PEAK_GINST,
+                             unit="G wave64 VALU instructions/s",
+                             frac=round(vg / VALU_PEAK_GINST, 4), insts_per_launch=valu,
+                             issue="1 wave64 instruction per SIMD per 4 cycles, "
+                                   "1024 SIMDs, 2.4 GHz")
+        roof = dict(bound="hbm", achieved=hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=hbm["frac"], traffic=None if traffic is None else round(traffic, 0),
+                    hbm=hbm, valu=valu_roof)
+        if valu_roof is not None and hbm["traffic_frac"] is not None and \
+                valu_roof["frac"] > hbm["traffic_frac"]:
+            roof.update(bound="alu", achieved=valu_roof["achieved"], peak=VALU_PEAK_GINST,
+                        unit=valu_roof["unit"], frac=valu_roof["frac"])
         left = float(rows[:, 3].sum() / max(1.0, rows[:, 2:4].sum()))
         extra["step_kernel"] = dict(kernel="k_step", launches=int(len(rows)),
                                     steps_per_launch=int(tune["sub_steps"]),
@@ -470,7 +590,8 @@ def main():
     torch.cuda.empty_cache()
     if args.workload == "batched" and not args.no_sequential:
         print("[bench] running the stacks one by one", file=sys.stderr, flush=True)
-        extra["sequential"] = sequential_leg(prob, wall / args.steps)
+        extra["sequential"] = sequential_leg(prob, wall / args.steps,
+                                             {k: v for k, v in extra["tuning"].items()})
         print(f"[bench] sequential: {extra['sequential']}", file=sys.stderr, flush=True)
     if args.workload == "batched" and not args.no_variants:
         print("[bench] physics variants", file=sys.stderr, flush=True)
@@ -482,6 +603,16 @@ def main():
         except Exception as e:  # reported, never hidden
             extra["adjoint"] = {"error": str(e)}
         print(f"[bench] adjoint: {extra['adjoint']}", file=sys.stderr, flush=True)
+
+    if args.multilayer_instances > 0:
+        print("[bench] multilayer forward + whole-tree adjoint leg", file=sys.stderr, flush=True)
+        try:
+            extra["multilayer_adjoint"] = multilayer_adjoint_leg(args.multilayer_instances,
+                                                                 args.tune_steps)
+        except Exception as e:  # reported, never hidden
+            extra["multilayer_adjoint"] = {"error": str(e)}
+        print(f"[bench] multilayer adjoint: {extra['multilayer_adjoint']}", file=sys.stderr,
+              flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -499,7 +630,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 decisions, f32 state" if not prob.state_fp64 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "instances": len(prob.instances),
                    "primaries": prob.n_primaries, "time_steps": prob.n_steps,
