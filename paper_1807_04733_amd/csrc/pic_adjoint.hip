@@ -265,6 +265,12 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       const bool alive0 = !(fl & kDead);
       bool died = false;
       AdjLane L{gi, lo, 0.0, false};
+      // pass 2: the tree's return, loaded before the half step so that its latency
+      // overlaps the transport arithmetic (score terms need it)
+      if (ADJ == 3 && alive0) {
+        L.R = A.R[lo];
+        L.haveR = true;
+      }
       const double mu_in = mu;
       const uint32_t E_in = E, fl_in = fl;
       if (alive0) {
@@ -419,10 +425,13 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       wave_sync();
     };
 
-    // next slot of this lane, fetched one iteration ahead (as in the forward step)
+    // next slot of this lane, fetched one iteration ahead (as in the forward step), with
+    // its partial return in pass 1 of the whole-tree estimator: only the carrier in the
+    // slot changes it, so the prefetched value is current when the lane gets there
     F nz = 0, nmu = 0;
     uint32_t nE = 0, nfl = kDead, nw = 1u << 16;
     uint64_t nu = 0;
+    double nr = 0.0;
     auto fetch = [&](int t) {
       if (t < tail0) {
         const int64_t g = base + t;
@@ -432,6 +441,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         nE = a.E[g];
         nu = a.uid[g];
         if (a.wt) nw = a.wt[g];
+        if (ADJ == 2) nr = A.r[g];
       } else {
         nfl = kDead;
       }
@@ -442,6 +452,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
       const F rz = nz, rmu = nmu;
       const uint32_t rE = nE, rfl = nfl, rw = nw;
       const uint64_t ru = nu;
+      const double rr = nr;
       fetch(t + (int)blockDim.x);
       const bool have = t < total;
       const bool from_soa = have && t < tail0;
@@ -469,7 +480,7 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
           if (ADJ != 3) {
             const double g = deposit_weight(A, I, et, zs, mu, rE, rfl, rw, s_edges, s_gcur);
             if (ADJ == 1 && g != 0.0) slow = true;
-            if (ADJ == 2 && g != 0.0) A.r[gi] += g;
+            if (ADJ == 2 && g != 0.0) A.r[gi] = rr + g;
           }
           if (!slow && a.z_write) {
             gz[gi] = (F)zs;
