@@ -32,13 +32,6 @@ constexpr int kSlowQ = (int)(kSlowQueueBytes / 4);  // general-path slots per wa
 // bytes per wave of the copies of the queued carriers' stored state
 template <typename F>
 constexpr size_t kAdjStageBytes = (size_t)kSlowQ * (2 * sizeof(F) + 20);
-constexpr int kNfShift = 16;
-constexpr uint32_t kNfMask = 0x7FFFu;
-
-__device__ __forceinline__ uint32_t nf_of(uint32_t fl) { return (fl >> kNfShift) & kNfMask; }
-__device__ __forceinline__ uint32_t with_nf(uint32_t fl, uint32_t nf) {
-  return (fl & ~(kNfMask << kNfShift)) | (nf << kNfShift);
-}
 
 // Per-lane adjoint bookkeeping of one carrier.
 struct AdjLane {

@@ -368,25 +368,29 @@ size_t lds_per_wg(int block) {
 // per-wave queues, then (where they fit) the per-wave copies of the sub-step-0 queue's
 // carrier state.  Fills the offsets in `a` (if given) and returns the bytes.
 size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, const int* cur_on,
-                   StepArgs* a, bool dens16 = false) {
+                   StepArgs* a, bool dens16 = false, int adj_pass = 0) {
   size_t off = 0;
   // a density slice: u64 weight sums, u32 counts, or 16-bit counts packed two per word
   const size_t dens_bytes = dens16 ? (size_t)c->lds_dens_words * 2
                                    : (size_t)c->lds_dens_words * dens_elem(c);
+  // the adjoint passes deposit no moments: pass 1 keeps its dL/d(current) slices where
+  // the current slices are, pass 2 its gradient accumulator
   for (int j = 0; j < kMaxSub; ++j) {
-    const bool d = j < n_sub && dens_on[j] && c->dens_lds;
+    const bool d = j < n_sub && dens_on[j] && c->dens_lds && adj_pass == 0;
     if (a) a->lds_dens_at[j] = d ? (int32_t)off : -1;
     if (d) off = (off + dens_bytes + 15) & ~(size_t)15;
   }
   if (a) a->dens16 = dens16 ? 1 : 0;
   for (int j = 0; j < kMaxSub; ++j) {
-    const bool u = j < n_sub && cur_on[j];
+    const bool u = j < n_sub && cur_on[j] && adj_pass != 2;
     if (a) a->lds_cur_at[j] = u ? (int32_t)off : -1;
     if (u) off = (off + (size_t)c->lds_cur_words * 8 + 15) & ~(size_t)15;
   }
+  if (a) a->lds_grad_at = adj_pass == 2 ? (int32_t)off : -1;
+  if (adj_pass == 2) off = (off + (size_t)c->plan.K * 8 + 15) & ~(size_t)15;
   // generation-moment slices (u32 per (z, spin)) beside the density slices in LDS
   for (int j = 0; j < kMaxSub; ++j) {
-    const bool g = j < n_sub && dens_on[j] && c->dens_lds && c->plan.off_gen >= 0;
+    const bool g = j < n_sub && dens_on[j] && c->dens_lds && c->plan.off_gen >= 0 && adj_pass == 0;
     if (a) a->lds_gen_at[j] = g ? (int32_t)off : -1;
     if (g) off = (off + (size_t)c->lds_cur_words * dens_elem(c) + 15) & ~(size_t)15;
   }
@@ -514,7 +518,11 @@ CompactArgs compact_args(const pic_ctx* c) {
   return a;
 }
 
-pic_status enqueue_steps(pic_ctx* c, int start, int n) {
+// Enqueue steps start .. start+n-1 of the forward run (adj_pass 0) or of a pass of the
+// whole-tree adjoint replayed by the step kernel (adj_pass 1: tree returns, 2: scores;
+// g_dens / g_cur the loss weights); same launch structure and tuning in every case.
+pic_status enqueue_steps(pic_ctx* c, int start, int n, int adj_pass = 0,
+                         const double* g_dens = nullptr, const double* g_cur = nullptr) {
   const bool fp64 = c->plan.state_bytes == 8;
   const int n_slabs = (int)c->plan.slab_inst.size();
   int grid = c->tune.grid > 0 ? c->tune.grid : 512;
@@ -528,6 +536,16 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
     // multiples of T, so only the last sub-step of a launch ever stores z
     int ns = std::min(T, start + n - s);
     StepArgs a = step_args(c, s);
+    if (adj_pass) {
+      a.adj_pass = adj_pass;
+      a.adj_r = c->at<double>(c->plan.off_r);
+      a.adj_R = c->at<double>(c->plan.off_R);
+      a.adj_gd = g_dens;
+      a.adj_gc = g_cur;
+      a.adj_grad = c->at<double>(c->plan.off_grad);
+      a.adj_K = c->plan.K;
+      a.gen = nullptr;
+    }
     int dens_on[kMaxSub] = {0, 0}, cur_on[kMaxSub] = {0, 0};
     for (int j = 0; j < kMaxSub; ++j) {
       const int sj = s + j;
@@ -537,7 +555,7 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
     // Two density slices of 32-bit counters that would cost a workgroup per CU are held as
     // 16-bit counters (unweighted runs without energy tables; the counts stay exact).
     bool dens16 = false;
-    if (ns > 1 && dens_on[0] && dens_on[1] && c->dens_lds && c->plan.off_w < 0 &&
+    if (adj_pass == 0 && ns > 1 && dens_on[0] && dens_on[1] && c->dens_lds && c->plan.off_w < 0 &&
         c->plan.etab_max == 0 &&
         step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) + step_static_lds() >
             lds_per_wg(c->tune.block))
@@ -546,8 +564,8 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
     // the first step would have to store z
     const bool first_writes = (s - start) % K == K - 1 || s == start + n - 1;
     if (ns > 1 && (first_writes ||
-                   step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr, dens16) >
-                       c->max_lds)) {
+                   step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr, dens16,
+                               adj_pass) > c->max_lds)) {
       ns = 1;
       dens_on[1] = cur_on[1] = 0;
       dens16 = false;
@@ -568,9 +586,9 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
     std::memset(&L, 0, sizeof(L));
     L.grid = grid;
     L.block = c->tune.block;
-    L.lds = step_layout(c, c->tune.block, ns, dens_on, cur_on, &a, dens16);
+    L.lds = step_layout(c, c->tune.block, ns, dens_on, cur_on, &a, dens16, adj_pass);
     hipEvent_t* ev = nullptr;
-    if (c->timing) {
+    if (c->timing && adj_pass == 0) {
       c->tev.emplace_back();
       c->tstep.push_back(s);
       c->tnsub.push_back(ns);
@@ -585,6 +603,7 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n) {
       compact = compact || (c->tune.compact_every > 0 && (s + j + 1) % c->tune.compact_every == 0);
     if (compact && !c->plan.debug && s + ns < c->cfg.n_steps) {
       CompactArgs ca = compact_args(c);
+      if (adj_pass == 1) ca.r = c->at<double>(c->plan.off_r);  // partial returns move along
       HIP_TRY(launch_compact(ca, fp64, c->stream));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[2], c->stream));
@@ -990,8 +1009,31 @@ static pic_status clear_particles(pic_ctx* c) {
   return PIC_OK;
 }
 
+// The whole-tree passes run in the step kernel's adjoint modes (two steps per launch, the
+// forward's tuning) for runs without energy tables, weights or debug counts; the replay
+// kernel k_adj covers the rest.
+static bool tree_passes_in_step_kernel(const pic_ctx* c) {
+  return c->plan.etab_max == 0 && c->plan.off_w < 0 && !c->plan.debug;
+}
+
 static pic_status replay(pic_ctx* c, int adj, const double* g_dens, const double* g_cur) {
   const Plan& p = c->plan;
+  if (adj >= 2 && tree_passes_in_step_kernel(c)) {
+    pic_status st = clear_particles(c);
+    if (st != PIC_OK) return st;
+    st = enqueue_steps(c, 0, c->cfg.n_steps, adj - 1, g_dens, g_cur);
+    if (st != PIC_OK) return st;
+    AdjArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.s = step_args(c, c->cfg.n_steps - 1);
+    A.r = c->at<double>(p.off_r);
+    A.R = c->at<double>(p.off_R);
+    A.grad = c->at<double>(p.off_grad);
+    A.K = p.K;
+    A.n_ch = c->inst[0].n_channels;
+    HIP_TRY(launch_adjoint_final(A, p.state_bytes == 8, adj, (uint32_t)c->cfg.n_steps, c->stream));
+    return PIC_OK;
+  }
   const bool fp64 = p.state_bytes == 8;
   const int n_slabs = (int)p.slab_inst.size();
   // at most 256 threads per workgroup; the grid keeps the forward's number of waves

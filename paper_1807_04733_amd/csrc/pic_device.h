@@ -249,13 +249,14 @@ __device__ __forceinline__ double replay_flights(double z, double vmh, int n) {
 }
 
 // Transport half step with the layer's table values cached (same arithmetic and draws
-// as half_push).
-template <bool ET>
+// as half_push); `on_hit` observes each interface decision as in half_push.
+template <bool ET, class OnHit = NoHitObserver>
 __device__ __forceinline__ void half_push_c(const DevInst& I, const double* et, bool tau2,
                                             LayCache& c, double& z, double& mu,
                                             uint32_t& fl, uint32_t E, uint32_t lo, uint32_t hi,
                                             uint32_t step, uint32_t tag, double h, uint32_t k0,
-                                            uint32_t k1, HitCounts& hc, bool& bad) {
+                                            uint32_t k1, HitCounts& hc, bool& bad,
+                                            OnHit on_hit = OnHit()) {
   double ze = z + (c.v * mu) * h;
   if (ze > c.zhi || ze < c.zlo) {
     int l = layer_of(fl);
@@ -279,7 +280,8 @@ __device__ __forceinline__ void half_push_c(const DevInst& I, const double* et, 
       }
       const int iface = up ? l : l - 1;
       const int nl = up ? l + 1 : l - 1;
-      const double T = trans_prob(I, I.tt[iface][up ? 0 : 1][s], E);
+      const int tab = I.tt[iface][up ? 0 : 1][s];
+      const double T = trans_prob(I, tab, E);
       bool go;
       if (T >= 1.0) {
         go = true;
@@ -290,6 +292,7 @@ __device__ __forceinline__ void half_push_c(const DevInst& I, const double* et, 
         go = u01(w.x) < T;
       }
       ++draws;
+      on_hit(tab, l, T, go);
       if (go) {
         if constexpr (ET) {
           const LayCache cn = load_lay<true>(I, et, tau2, nl, s, E);

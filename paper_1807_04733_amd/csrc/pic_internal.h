@@ -36,6 +36,14 @@ constexpr uint32_t kStampMask = 0x7u;
 constexpr int kMaxZEvery = 8;
 // Steps one launch of the step kernel may advance.
 constexpr int kMaxSub = 2;
+// Adjoint replays: the first step whose non-event score term of a carrier is still pending
+// lives in flag bits 16-30 (the forward never sets them).
+constexpr int kNfShift = 16;
+constexpr uint32_t kNfMask = 0x7FFFu;
+__host__ __device__ __forceinline__ uint32_t nf_of(uint32_t fl) { return (fl >> kNfShift) & kNfMask; }
+__host__ __device__ __forceinline__ uint32_t with_nf(uint32_t fl, uint32_t nf) {
+  return (fl & ~(kNfMask << kNfShift)) | (nf << kNfShift);
+}
 
 // Energy-bin lookup table: one entry per bucket of 2^22 energy units (the top 10 bits).
 constexpr int kEBucketShift = 22;
@@ -138,6 +146,18 @@ struct StepArgs {
   // per-wave copies of the state of the carriers in the sub-step-0 queue (stage_wave_bytes
   // per wave), so that their general pass reads LDS instead of HBM; -1: not staged
   int32_t lds_stage_at;
+  // The two passes of the whole-tree adjoint run by the step kernel itself (modes
+  // kModeRet, kModeScore of pic_kernels.hip), with the forward's launch structure:
+  // per-slot partial returns, per-root returns, dL/d(density), dL/d(current) (pass 1
+  // copies the launch's slices into LDS at lds_cur_at), the gradient and its length, and
+  // the LDS gradient accumulator of pass 2 (doubles [adj_K] at lds_grad_at).
+  double* adj_r;
+  double* adj_R;
+  const double* adj_gd;
+  const double* adj_gc;
+  double* adj_grad;
+  int32_t adj_pass;            // 0: forward; 1, 2: the whole-tree adjoint's passes
+  int32_t adj_K, lds_grad_at;
 };
 
 struct AdjArgs {

@@ -37,6 +37,15 @@ constexpr int kModeDensGlobal = 4;  // density with global atomics (its LDS slic
 constexpr int kModeTab = 8;         // energy-dependent speeds and rates (tables in LDS)
 constexpr int kModeWt = 16;         // weighted superparticles (StepArgs::wt)
 constexpr int kModeDens16 = 32;     // density slices as 16-bit counters, two per LDS word
+// The whole-tree likelihood-ratio adjoint replays the run twice with the same dynamics and
+// launch structure as the forward (two steps per launch from registers where carriers stay
+// on the common path).  Pass 1 deposits nothing: each deposit adds its weight in the loss,
+// dL/d(density) + dL/d(current) v cos(theta), to the carrier's partial return, and the
+// partial returns add up to the return R of each primary tree.  Pass 2 adds every score
+// term of the tree's random decisions times R to the gradient (the non-event terms of a
+// carrier lazily, from the first pending step kept in its flags).
+constexpr int kModeRet = 64;        // whole-tree adjoint, pass 1
+constexpr int kModeScore = 128;     // whole-tree adjoint, pass 2
 
 // Compile-time sub-step index for the generic lambdas of k_step.
 template <int V>
@@ -76,10 +85,26 @@ __device__ __forceinline__ void dens16_wrap(unsigned long long* g, int idx, uint
 template <int MODE, int J>
 __device__ __forceinline__ void deposit_v(const StepArgs& a, const DevInst& I, unsigned char* dyn,
                                           double z, int eb, uint32_t fl, long long val,
-                                          uint32_t wfx) {
+                                          uint32_t wfx, double& racc) {
+  if constexpr ((MODE & kModeScore) != 0) return;  // adjoint pass 2: no moments
   int zb = (int)floor(z * I.inv_dz);
   zb = zb < 0 ? 0 : (zb > I.nz - 1 ? I.nz - 1 : zb);
   const int s = (int)(fl & kSpinMask);
+  if constexpr ((MODE & kModeRet) != 0) {
+    // adjoint pass 1: the deposit's weight in the loss joins the carrier's partial return
+    double g = 0.0;
+    if (a.sub_dens_on[J] && a.adj_gd) {
+      const double gd = a.adj_gd[I.dens_off +
+                                 (((int64_t)a.sub_dens_slot[J] * I.nz + zb) * a.n_ebins + eb) * 2 + s];
+      g += weighted<MODE>(a) ? gd * ((double)wfx * 0x1p-16) : gd;
+    }
+    if (a.sub_cur_on[J] && a.adj_gc) {
+      const double gc = ((const double*)(dyn + a.lds_cur_at[J]))[zb * 2 + s];
+      if (gc != 0.0) g += gc * ((double)val * 0x1p-32);
+    }
+    if (g != 0.0) racc += g;
+    return;
+  }
   if (a.sub_dens_on[J]) {
     const int idx = (zb * a.n_ebins + eb) * 2 + s;
     const bool wtd = weighted<MODE>(a);
@@ -134,10 +159,68 @@ template <int MODE, int J>
 __device__ __forceinline__ void deposit(const StepArgs& a, const DevInst& I, unsigned char* dyn,
                                         const uint32_t* s_edges, const uint8_t* s_ebkt, double z,
                                         double mu, uint32_t E, uint32_t fl, double v,
-                                        uint32_t wfx) {
+                                        uint32_t wfx, double& racc) {
+  if constexpr ((MODE & kModeScore) != 0) return;
   const int eb = a.sub_dens_on[J] ? ebin(a, s_edges, s_ebkt, E) : 0;
-  deposit_v<MODE, J>(a, I, dyn, z, eb, fl, cur_val<MODE>(a, v, mu, wfx), wfx);
+  deposit_v<MODE, J>(a, I, dyn, z, eb, fl, cur_val<MODE>(a, v, mu, wfx), wfx, racc);
 }
+
+// Score terms of adjoint pass 2: added to the workgroup's gradient accumulator in LDS,
+// times the return R of the carrier's tree.
+struct TreeScore {
+  double* s_grad;
+  double R;
+  __device__ __forceinline__ void add(int k, double v) const { atomicAdd(&s_grad[k], v * R); }
+  // the pending non-event terms, +x_in for each step from the first pending one to upto-1
+  // (a constant channel), folded in
+  __device__ __forceinline__ void flush(uint32_t& fl, uint32_t upto, int chan, double x_in) const {
+    const uint32_t nf = nf_of(fl);
+    if (upto > nf) {
+      add(chan, (double)(upto - nf) * x_in);
+      fl = with_nf(fl, upto);
+    }
+  }
+};
+
+// Interface decisions of a half step in adjoint pass 2: the pending non-event terms of the
+// channel before the hit, then the score of the transmission draw on the table nodes that
+// the carrier's energy interpolates, w0/T and w1/T if transmitted, -w/(1-T) if reflected.
+struct HitTreeScore {
+  const TreeScore& ts;
+  const DevInst& I;
+  const double* et;
+  bool tau2;
+  double dt;
+  uint32_t& fl;
+  uint32_t E;
+  uint32_t upto;
+  __device__ __forceinline__ void operator()(int tab, int layer, double T, bool go) const {
+    const int s = (int)(fl & kSpinMask);
+    ts.flush(fl, upto, I.chi[layer][s], dt * inel_rate_at(I, et, tau2, layer, s, E));
+    const int TE = I.t_entries;
+    int k0 = 0;
+    double w0 = 1.0, w1 = 0.0;
+    if (TE > 1) {
+      const double x = ((double)E * 0x1p-30) * I.T_scale;
+      const int k = (int)floor(x);
+      if (k >= TE - 1) {
+        k0 = TE - 1;
+      } else {
+        k0 = k;
+        w1 = x - (double)k;
+        w0 = 1.0 - w1;
+      }
+    }
+    const int base = (int)I.n_ch + tab * TE + k0;
+    if (go) {
+      ts.add(base, w0 / T);
+      if (w1 != 0.0) ts.add(base + 1, w1 / T);
+    } else {
+      ts.add(base, -w0 / (1.0 - T));
+      if (w1 != 0.0) ts.add(base + 1, -w1 / (1.0 - T));
+    }
+  }
+};
 
 // Merge one LDS histogram slice of n entries (u32 or u64) into int64 bins (non-zero
 // entries only) and clear it.
@@ -218,6 +301,7 @@ struct SlabPtrs {
   uint32_t* fl;
   uint64_t* ev;
   uint32_t* w;
+  double* r;     // adjoint pass 1: partial returns
 };
 
 // Element i of a slab array, addressed with a 32-bit byte offset from the slab's base
@@ -253,6 +337,9 @@ template <typename F, int T, int MODE>
 __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   constexpr bool ET = (MODE & kModeTab) != 0;
+  constexpr bool RET = (MODE & kModeRet) != 0;      // adjoint pass 1
+  constexpr bool SCORE = (MODE & kModeScore) != 0;  // adjoint pass 2
+  constexpr bool ADJP = RET || SCORE;
   // dynamic LDS: [histogram slices of the sub-steps | energy tables | per wave: newborn
   // queue, slot queue of sub-step 0 (, of sub-step 1) | per wave, where they fit: copies of
   // the stored state of the sub-step-0 queue's carriers]; offsets set by the host
@@ -301,6 +388,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   const double* const et = ET ? (const double*)(dyn + a.lds_etab_at) : nullptr;
   const bool tau2 = a.tau_exp2 != 0;
   const bool WT = weighted<MODE>(a);
+  double* const s_grad = SCORE ? (double*)(dyn + a.lds_grad_at) : nullptr;
   constexpr uint32_t kW1 = 1u << 16;  // weight 1
   int cur_inst = -1;
   bool bad = false;
@@ -312,7 +400,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     if (slab >= a.n_slabs) break;
     const int inst = a.slab_inst[slab];
     if (inst != cur_inst) {
-      if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
+      if constexpr (ADJP) {
+        if (cur_inst >= 0) __syncthreads();  // every wave is done with the old tables
+      } else {
+        if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
+      }
       const uint4* src = (const uint4*)&a.inst[inst];
       uint4* dst = (uint4*)&s_inst;
       for (int i = tid; i < a.inst_bytes / 16; i += blockDim.x) dst[i] = src[i];
@@ -322,6 +414,16 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         const double* tsrc = a.etab + G.etab_off;
         double* tdst = (double*)(dyn + a.lds_etab_at);
         for (int i = tid; i < n; i += blockDim.x) tdst[i] = tsrc[i];
+      }
+      if constexpr (RET) {
+        // this instance's dL/d(current) slices of the launch's steps
+        const DevInst& G = a.inst[inst];
+        for (int j = 0; j < T; ++j)
+          if (a.sub_cur_on[j] && a.adj_gc) {
+            const double* gsrc = a.adj_gc + G.cur_off + (int64_t)a.sub_cur_slot[j] * G.nz * 2;
+            double* gdst = (double*)(dyn + a.lds_cur_at[j]);
+            for (int i = tid; i < G.nz * 2; i += blockDim.x) gdst[i] = gsrc[i];
+          }
       }
       cur_inst = inst;
     }
@@ -357,7 +459,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       }
     }
     const SlabPtrs<F> sp{gz + base, gmu + base, a.E + base, a.uid + base, a.flags + base,
-                         DEBUG ? a.ev + base : nullptr, WT ? a.wt + base : nullptr};
+                         DEBUG ? a.ev + base : nullptr, WT ? a.wt + base : nullptr,
+                         RET ? a.adj_r + base : nullptr};
     LaneCounts lc[T];
 #pragma unroll
     for (int j = 0; j < T; ++j) lc[j] = LaneCounts{0, 0, 0, 0};
@@ -408,11 +511,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // needed), or the slot goes to the sub-step's queue.  `slot` holds the carrier whose
     // stored z is that position (stamp = this sub-step's phase).
     auto cont = [&](auto sub, bool act, uint32_t slot, double z, double mu, uint32_t E,
-                    uint32_t fl, uint32_t lo, uint32_t hi, uint32_t wfx)
+                    uint32_t fl, uint32_t lo, uint32_t hi, uint32_t wfx, double racc)
                     __attribute__((always_inline)) {
       constexpr int J = decltype(sub)::value;
       bool left = false;
       if (act) {
+        const double r_in = racc;
         const int l = layer_of(fl);
         const LayCache c = load_lay<ET>(I, et, tau2, l, (int)(fl & kSpinMask), E);
         const double zm = z + (c.v * mu) * a.h;
@@ -423,13 +527,14 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
         if (!left) {
           const double zs = to_store<F>(ze);
-          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v, wfx);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v, wfx, racc);
           lc[J].dep += 1;
           n_fast[J] += 1;
           if (a.sub_z_write[J]) {
             at(sp.z, slot) = (F)zs;
             if ((fl >> kStampShift) & kStampMask) at(sp.fl, slot) = fl & ~(kStampMask << kStampShift);
           }
+          if (RET && racc != r_in) at(sp.r, slot) = racc;
         }
       }
       push(sub, left, slot);
@@ -443,7 +548,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // the step, with its state and its slot.
     auto general = [&](auto sub, bool from_soa, bool is_new, uint32_t gi, double& z, double& mu,
                        uint32_t& E, uint32_t& fl, uint32_t lo, uint32_t hi, uint64_t evp,
-                       uint32_t wfx, uint32_t& slot) __attribute__((always_inline)) -> bool {
+                       uint32_t wfx, uint32_t& slot, double& racc) __attribute__((always_inline))
+                       -> bool {
       constexpr int J = decltype(sub)::value;
       const uint32_t step = step0 + J;
       // stamp of the z this sub-step stores (0 when it ends a write-back period)
@@ -454,12 +560,22 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       double zmid = 0.0;
       uint32_t E2 = 0, flmid = 0;
       HitCounts hc{0, 0, 0};
+      // adjoint pass 2: the tree's return, loaded before the half step so that its latency
+      // overlaps the transport arithmetic
+      TreeScore ts{s_grad, 0.0};
+      if (SCORE && alive0) ts.R = a.adj_R[lo];
       if (alive0) {
         const double mu_in = mu;
         const uint32_t fl_in = fl;
         LayCache c = load_lay<ET>(I, et, tau2, layer_of(fl), (int)(fl & kSpinMask), E);
-        half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0,
-                        a.key1, hc, bad);
+        if constexpr (SCORE) {
+          const uint32_t E_now = E;
+          half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0,
+                          a.key1, hc, bad, HitTreeScore{ts, I, et, tau2, a.dt, fl, E_now, step});
+        } else {
+          half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0,
+                          a.key1, hc, bad);
+        }
         // ---- scattering over the full step, at the mid-step state
         const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
         const double itel = I.lay[layer_of(fl)].z;
@@ -475,6 +591,19 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           event = true;
         } else {
           event = u0 < -expm1(-x);
+        }
+        if (SCORE && event) {
+          // the event's score (Eq. 2), after the channel's pending non-event terms, and the
+          // channel choice's (Eqs. 5, 8); non-event terms pend again from the next step
+          const int cch = I.chi[layer_of(fl)][fl & kSpinMask];
+          const double x_in = a.dt * inel_rate<ET>(c, tau2, E);
+          ts.flush(fl, step, cch, x_in);
+          const double prob = -expm1(-x);
+          ts.add(cch, -x_in * exp(-x) / prob);
+          const bool removed = a.absorb_next && E < a.e_min;
+          if (itel > 0.0 && !removed)
+            ts.add(cch, u01(w.y) < itel / rate ? x_in / x : -1.0 + x_in / x);
+          fl = with_nf(fl, step + 1);
         }
         if (event && a.absorb_next && E < a.e_min) {
           // a carrier of the lowest energy bin leaves the population at its next event
@@ -519,14 +648,23 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           // with energy tables the speed and rate follow the new energy
           if constexpr (ET)
             if (dirty & 2u) c = load_lay<ET>(I, et, tau2, layer_of(fl), (int)(fl & kSpinMask), E);
-          half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
-                          a.key1, hc, bad);
+          if constexpr (SCORE) {
+            const uint32_t E_now = E;
+            half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
+                            a.key1, hc, bad,
+                            HitTreeScore{ts, I, et, tau2, a.dt, fl, E_now, step + 1});
+          } else {
+            half_push_c<ET>(I, et, tau2, c, z, mu, fl, E, lo, hi, step, kTagHalf2, a.h, a.key0,
+                            a.key1, hc, bad);
+          }
           z = to_store<F>(z);
-          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, z, mu, E, fl, c.v, wfx);
+          deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, z, mu, E, fl, c.v, wfx, racc);
           lc[J].dep += 1;
         } else {
           z = to_store<F>(z);
           fl |= kDead;
+          // adjoint pass 1: the partial return goes to the tree's return
+          if (RET && racc != 0.0) atomicAdd(&a.adj_R[lo], racc);
         }
         // z is stored below: the stamp says at which step of the write-back period
         fl = (fl & ~(kStampMask << kStampShift)) | (died ? 0u : z_next << kStampShift);
@@ -586,6 +724,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         if (dirty & 2u) at(sp.E, gi) = E;
         if (dirty & 4u) at(sp.fl, gi) = fl;
         if (DEBUG) at(sp.ev, gi) = evp;
+        if (RET && !died) at(sp.r, gi) = racc;
       }
       // the slab's dead count: carriers that died in a slot of the slab (a new primary that
       // found no free slot is not one), so that tail - dead is the live count
@@ -614,6 +753,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       double cmu = 0.0;
       uint32_t cfl = kDead, lin = 0, pos = 0;
       bool placed = false;
+      double cr = 0.0;  // adjoint pass 1: the newborn's own partial return
       if (act) {
         const uint4 sw = philox10(lo, phi, step, kTagSpawn, a.key0, a.key1);
         const int l = layer_of(pfl);
@@ -625,12 +765,21 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           if (lin == phi) lin ^= 2u;
         }
         cfl = cs | (pfl & ~kSpinMask) | (z_next << kStampShift);
+        // adjoint pass 2: a newborn's non-event terms start with the next step
+        if (SCORE) cfl = with_nf(cfl, step + 1);
         HitCounts h{0, 0, 0};
         LayCache cc = load_lay<ET>(I, et, tau2, l, (int)cs, cE);
-        half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h, a.key0,
-                        a.key1, h, bad);
+        if constexpr (SCORE) {
+          const TreeScore cts{s_grad, a.adj_R[lo]};
+          half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h,
+                          a.key0, a.key1, h, bad,
+                          HitTreeScore{cts, I, et, tau2, a.dt, cfl, cE, step + 1});
+        } else {
+          half_push_c<ET>(I, et, tau2, cc, cz, cmu, cfl, cE, lo, lin, step, kTagHalf2, a.h,
+                          a.key0, a.key1, h, bad);
+        }
         cz = to_store<F>(cz);
-        deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, cz, cmu, cE, cfl, cc.v, cw);
+        deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, cz, cmu, cE, cfl, cc.v, cw, cr);
         lc[J].dep += 1;
         lc[J].tr += h.tr;
         lc[J].ri += h.ri;
@@ -650,17 +799,18 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           at(sp.fl, pos) = cfl;
           if (WT) at(sp.w, pos) = cw;
           if (DEBUG) at(sp.ev, pos) = ((uint64_t)h.tr << 16) + ((uint64_t)(h.ri + h.rs) << 32);
+          if (RET) at(sp.r, pos) = cr;
         } else {
           atomicOr(a.status, kStOverflow);
         }
       }
-      if constexpr (J + 1 < T) cont(Sub<J + 1>{}, placed, pos, cz, cmu, cE, cfl, lo, lin, cw);
+      if constexpr (J + 1 < T) cont(Sub<J + 1>{}, placed, pos, cz, cmu, cE, cfl, lo, lin, cw, cr);
     };
 
     // re-read the top n slots of a sub-step's queue and bring z to the start of that step
     auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, bool staged, uint32_t& g,
                          double& z, double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo,
-                         uint32_t& hi, uint64_t& evp, uint32_t& wfx)
+                         uint32_t& hi, uint64_t& evp, uint32_t& wfx, double& racc)
                          __attribute__((always_inline)) -> bool {
       wave_sync();
       const bool act = lane < n;
@@ -700,6 +850,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         hi = (uint32_t)(u >> 32);
         if (DEBUG) evp = at(sp.ev, g);
         wfx = WT ? at(sp.w, g) : kW1;
+        if (RET) racc = at(sp.r, g);
         const int d = phase - (int)((fl >> kStampShift) & kStampMask);
         if (d > 0) {
           const double v = ET ? speed_at(I, et, layer_of(fl), (int)(fl & kSpinMask), E)
@@ -713,12 +864,12 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     // of its queue
     auto drain_last = [&](int n) __attribute__((always_inline)) {
       uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
-      double z = 0.0, mu = 0.0;
+      double z = 0.0, mu = 0.0, racc = 0.0;
       uint64_t evp = 0;
       const bool act = pop_state(T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
                                  a.sub_z_phase[T - 1], T == 1 && STG, g, z, mu, E, fl, lo, hi,
-                                 evp, wfx);
-      general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
+                                 evp, wfx, racc);
+      general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot, racc);
       drain_kids(Sub<T - 1>{});
     };
     // ---- sub-step 0 of a two-step launch through the general path for the top n slots
@@ -726,13 +877,13 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     auto drain_first = [&](int n) __attribute__((always_inline)) {
       if constexpr (T > 1) {
         uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
-        double z = 0.0, mu = 0.0;
+        double z = 0.0, mu = 0.0, racc = 0.0;
         uint64_t evp = 0;
-        const bool act =
-            pop_state(SQ0, sn0, n, a.sub_z_phase[0], STG, g, z, mu, E, fl, lo, hi, evp, wfx);
+        const bool act = pop_state(SQ0, sn0, n, a.sub_z_phase[0], STG, g, z, mu, E, fl, lo, hi,
+                                   evp, wfx, racc);
         const bool surv =
-            general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot);
-        cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi, wfx);
+            general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot, racc);
+        cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi, wfx, racc);
         drain_kids(Sub<0>{});
       }
     };
@@ -769,8 +920,10 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         int l = 0;
         for (int q = 1; q < I.n_layers; ++q)
           if (I.lay[q].x <= z) l = q;
-        const uint32_t fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift) |
-                            ((uint32_t)a.sub_z_phase[J] << kStampShift);
+        uint32_t fl = s | ((uint32_t)l << kLayerShift) | (1u << kGenShift) |
+                      ((uint32_t)a.sub_z_phase[J] << kStampShift);
+        // adjoint pass 2: a primary's non-event terms start with its first step
+        if (SCORE) fl = with_nf(fl, step0 + J);
         if (WT) {
           // weight of the primary (Eq. 10), from the weight rows behind the energy tables
           const uint32_t wfx = primary_weight(
@@ -791,6 +944,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           at(sp.uid, pos) = qu;
           at(sp.fl, pos) = qfl;
           if (DEBUG) at(sp.ev, pos) = 0;
+          if (RET) at(sp.r, pos) = 0.0;
         } else {
           atomicOr(a.status, kStOverflow);
         }
@@ -807,6 +961,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     F nz = 0, nmu = 0;
     uint32_t nE = 0, nfl = kDead;
     uint64_t nu = 0;
+    double nr = 0.0;  // adjoint pass 1: the slot's partial return (only its carrier changes it)
     auto fetch = [&](int t) __attribute__((always_inline)) {
       if (t < tail0) {
         const uint32_t g = (uint32_t)t;
@@ -815,6 +970,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nmu = at(sp.mu, g);
         nE = at(sp.E, g);
         nu = at(sp.uid, g);
+        if (RET) nr = at(sp.r, g);
       } else {
         nfl = kDead;
       }
@@ -831,6 +987,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         const F rz = nz, rmu = nmu;
         const uint32_t rE = nE, rfl = nfl;
         const uint64_t ru = nu;
+        const double rr = nr;
         fetch(t + (int)blockDim.x);
         // the weight is read for the current tile only (not prefetched): one register less
         // held across the iteration
@@ -843,6 +1000,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
 
         // ---- the common steps of this launch, from registers
         int left_at = -1;
+        double racc = rr;
         if (from_soa && !(rfl & kDead)) {
           const int l = layer_of(rfl), s = (int)(rfl & kSpinMask);
           const LayCache c = load_lay<ET>(I, et, tau2, l, s, rE);
@@ -869,9 +1027,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                 left_at = j;
               } else {
                 z = to_store<F>(ze);
-                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, z, eb, rfl, cv, rw);
+                if (j == 0) deposit_v<MODE, 0>(a, I, dyn, z, eb, rfl, cv, rw, racc);
                 if constexpr (T > 1)
-                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, z, eb, rfl, cv, rw);
+                  if (j == 1) deposit_v<MODE, T - 1>(a, I, dyn, z, eb, rfl, cv, rw, racc);
                 lc[j].dep += 1;
                 n_fast[j] += 1;
               }
@@ -881,6 +1039,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
             at(sp.z, gi) = (F)z;
             if (st) at(sp.fl, gi) = rfl & ~(kStampMask << kStampShift);
           }
+          // adjoint pass 1: the return of the common steps, stored before a general pass
+          // of sub-step 1 re-reads it
+          if (RET && left_at != 0 && racc != rr) at(sp.r, gi) = racc;
         }
         push0(left_at == 0, gi, rz, rmu, rE, rfl, ru);
         if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi);
@@ -913,8 +1074,18 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       a.slab_dead[slab] += s_dead;
     }
   }
-  if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
+  if constexpr (!ADJP)
+    if (cur_inst >= 0) flush_all<MODE, T>(a, s_inst, dyn);
   if (bad) atomicOr(a.status, kStHits);
+  if constexpr (ADJP) {
+    // the replays leave the forward's counters alone; pass 2 hands in its gradient
+    if constexpr (SCORE) {
+      __syncthreads();
+      for (int k = tid; k < a.adj_K; k += blockDim.x)
+        if (s_grad[k] != 0.0) atomicAdd(&a.adj_grad[k], s_grad[k]);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < T; ++j) {
     if (n_fast[j]) atomicAdd(&s_fast[j], (unsigned long long)n_fast[j]);
@@ -1057,7 +1228,7 @@ static void launch_mode(const StepArgs& a, const StepLaunch& L, hipStream_t s) {
 
 // the launch modes that are instantiated: debug x density placement x tables x weights
 using StepModes = std::integer_sequence<int, 0, 1, 4, 5, 8, 9, 12, 13, 16, 17, 20, 21, 24, 25,
-                                        28, 29, 32, 33>;
+                                        28, 29, 32, 33, 64, 128>;
 
 template <typename F, int T, int... Ms>
 static hipError_t launch_any(const StepArgs& a, int mode, const StepLaunch& L, hipStream_t s,
@@ -1101,9 +1272,11 @@ hipError_t set_step_lds_limit(size_t bytes) {
 
 hipError_t launch_step(const StepArgs& a, bool fp64, const StepLaunch& L, hipStream_t s) {
   const bool dens_any = a.sub_dens_on[0] || (a.n_sub > 1 && a.sub_dens_on[1]);
-  const int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
-                   (a.etab_words > 0 ? kModeTab : 0) | (a.wt ? kModeWt : 0) |
-                   (dens_any && a.dens16 ? kModeDens16 : 0);
+  int mode = (a.debug ? kModeDebug : 0) | (dens_any && !a.dens_lds ? kModeDensGlobal : 0) |
+             (a.etab_words > 0 ? kModeTab : 0) | (a.wt ? kModeWt : 0) |
+             (dens_any && a.dens16 ? kModeDens16 : 0);
+  // the whole-tree adjoint's passes (plain runs only: the host checks)
+  if (a.adj_pass) mode = a.adj_pass == 1 ? kModeRet : kModeScore;
   if (L.ev[0]) (void)hipEventRecord(L.ev[0], s);
   hipError_t e;
   if (a.n_sub == 2)
