@@ -60,13 +60,14 @@ __device__ __forceinline__ bool weighted(const StepArgs& a) {
 }
 
 // A 16-bit density counter of the LDS slice wrapped (rare: 65536 deposits into one bin of
-// one workgroup's slice).  The 32-bit word holds bin 2k in its low and bin 2k+1 in its high
-// half and only ever receives additions, so every wrap of a half is seen by exactly the
-// atomic that causes it (from the value it returns): that lane moves 65536 into the
-// int64 bin, and a carry out of the low half into the high half is taken back out at once
-// (a wrap of the high half caused by the carry or by taking it back out is counted the
-// same way).  The slice then holds every bin's count modulo 65536 and the int64 bins the
-// rest, exactly, whatever the order of the concurrent additions.
+// one workgroup's slice).  The 32-bit word k holds bin 2k (spin up of a cell) in its low
+// and bin 2k+1 (spin down) in its high half and only ever receives additions, so every
+// wrap of a half is seen by exactly the atomic that causes it (from the value it returns):
+// that lane moves 65536 into the int64 bin, and a carry out of the low half into the high
+// half is taken back out at once (a wrap of the high half caused by the carry or by taking
+// it back out is counted the same way).  The slice then holds every bin's count modulo
+// 65536 and the int64 bins the rest, exactly, whatever the order of the concurrent
+// additions.
 __device__ __forceinline__ void dens16_wrap(unsigned long long* g, int idx, uint32_t sh,
                                             uint32_t old, uint32_t* wd) {
   atomicAdd(&g[idx], 65536ull);
@@ -235,7 +236,8 @@ __device__ __forceinline__ void merge_slice(U* s, unsigned long long* g, int n) 
   }
 }
 
-// The same for a slice of n 16-bit counters packed two per 32-bit word (n even).
+// The same for a slice of n 16-bit counters packed two per 32-bit word (n even; word k
+// holds bins 2k and 2k+1).
 __device__ __forceinline__ void merge_slice16(uint32_t* s, unsigned long long* g, int n) {
   for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
     const uint32_t v = s[b];
