@@ -10,8 +10,8 @@
  *
  * Readings of the paper that the text leaves open (the same list is kept with the
  * design notes): the scattering probability in one step is p = 1 - exp(-dt/tau_eff)
- * (Sec. III.A, "probability for one of the events to happen within dt") with at most
- * one event per step evaluated at the mid-step state; an inelastic event splits E into
+ * (Sec. III.A: the chance that some event occurs during the step) with at most one
+ * event per step evaluated at the mid-step state; an inelastic event splits E into
  * uE (kept by the scattering carrier, Eq. 7: uniform final energy) and (1-u)E (the
  * secondary, energy conservation); both products below E_min are removed at once;
  * newborn secondaries receive only the second transport half step in their birth
@@ -19,7 +19,9 @@
  *
  * Random numbers: Philox4x32-10 keyed by the seed, counter = (uid_lo, uid_hi, step, tag)
  * with one fixed tag per purpose, so every draw is a pure function of
- * (seed, particle, step, purpose) and independent of processing order.
+ * (seed, particle, step, purpose) and independent of processing order.  The event
+ * decisions of the two steps 2m and 2m+1 share one counter (step field 2m, tag DECIDE):
+ * word 0 decides step 2m, word 1 step 2m+1.
  *
  * Compile with -ffp-contract=off: every decision is taken on IEEE binary64 results of
  * the operations written here, in this order.
@@ -38,6 +40,7 @@
 #define TAG_HALF1  0x200u
 #define TAG_HALF2  0x300u
 #define TAG_INJECT 0x400u
+#define TAG_DECIDE 0x500u
 #define MAX_HITS   8
 #define MAX_LAYERS 16
 
@@ -254,8 +257,9 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
   const orc_problem* P = W->P;
   const orc_instance* I = W->I;
   const int l = p->layer, c = I->ch_of[l * 2 + p->spin];
-  uint32_t w[4];
-  draw(P, p->root, p->lin, (uint32_t)n, TAG_SCAT, w);
+  uint32_t d[4], w[4];
+  /* the event decision of step n: word n mod 2 of the pair counter (step field n - n mod 2) */
+  draw(P, p->root, p->lin, (uint32_t)n & ~1u, TAG_DECIDE, d);
   /* Eq. (2): 1/tau_eff = 1/tau_el + 1/tau(E); 1/tau(E) = inv_tau0 * Ek with Ek = (E/1 eV)^
    * tau_exp, or the channel's rate table */
   const double Ek = rate_shape(P, I, c, p->E);
@@ -263,11 +267,13 @@ static int scatter(worker* W, particle* p, int n, particle* child) {
   const double x = P->dt * rate;
   const double prob = -expm1(-x);
   const double x_in = P->dt * (Ek * I->inv_tau0[c]);
-  if (!(unif(w[0]) < prob)) {
+  if (!(unif(d[n & 1]) < prob)) {
     add_score(W, p, c, x_in);            /* d/d ln tau0 of log(1 - p) */
     return 0;
   }
   add_score(W, p, c, -x_in * exp(-x) / prob);
+  /* the event's own words: 1 channel, 2 new direction, 3 energy split (word 0 unused) */
+  draw(P, p->root, p->lin, (uint32_t)n, TAG_SCAT, w);
   p->ev[0]++;
   if (P->absorb_next && p->E < P->e_min_fx) {
     /* Sec. III.A: a carrier of the lowest energy bin leaves the hot population at its

@@ -273,7 +273,6 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
           half_push(I, z, mu, fl, E, lo, hi, step, kTagHalf1, a.h, a.key0, a.key1, hc, bad, et,
                     hs);
         }
-        const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
         const int l = layer_of(fl);
         const int s = (int)(fl & kSpinMask);
         const double itel = I.lay[l].z;
@@ -281,12 +280,14 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         const double rate = inel + itel;
         const double x = a.dt * rate;
         const double x_in = a.dt * inel;
-        const double u0 = u01(w.x);
+        const double u0 = u01(decide_word(lo, hi, step, a.key0, a.key1));
         bool event;
         if (u0 >= x) event = false;
         else if (x >= 0x1p-20 && u0 < x - 0.5 * x * x) event = true;
         else event = u0 < -expm1(-x);
         if (event) {
+          // the event's own words: channel (y), new direction (z), energy split (w)
+          const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
           const int c = I.chi[l][s];
           ops.flush(L, fl, step, c, x_in);
           const double prob = -expm1(-x);
@@ -462,11 +463,10 @@ __global__ void __launch_bounds__(256, 4) k_adj(AdjArgs A) {
         const uint32_t st = (rfl >> kStampShift) & kStampMask;
         const double z0 = replay_flights<F>((double)rz, (c.v * mu) * a.h, a.z_phase - (int)st);
         const double zm = z0 + (c.v * mu) * a.h;
-        const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step, kTagScat, a.key0,
-                                 a.key1);
+        const uint32_t wd = decide_word((uint32_t)ru, (uint32_t)(ru >> 32), step, a.key0, a.key1);
         const double x = a.dt * (c.itau + I.lay[l].z);
         const double ze = zm + (c.v * mu) * a.h;
-        slow = zm > c.zhi || zm < c.zlo || u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        slow = zm > c.zhi || zm < c.zlo || u01(wd) < x || ze > c.zhi || ze < c.zlo;
         if (!slow) {
           const double zs = to_store<F>(ze);
           const int64_t gi = base + t;

@@ -48,6 +48,18 @@ __device__ __forceinline__ uint4 philox10(uint32_t x0, uint32_t x1, uint32_t x2,
   return make_uint4(x0, x1, x2, x3);
 }
 
+// The event-decision words of the step pair (2m, 2m + 1) holding `step`: one generator
+// call serves both steps of the pair (word 0 decides step 2m, word 1 step 2m + 1).
+__device__ __forceinline__ uint4 decide_pair(uint32_t lo, uint32_t hi, uint32_t step, uint32_t k0,
+                                             uint32_t k1) {
+  return philox10(lo, hi, step & ~1u, kTagDecide, k0, k1);
+}
+__device__ __forceinline__ uint32_t decide_word(uint32_t lo, uint32_t hi, uint32_t step,
+                                                uint32_t k0, uint32_t k1) {
+  const uint4 w = decide_pair(lo, hi, step, k0, k1);
+  return (step & 1u) ? w.y : w.x;
+}
+
 // uniform on (0,1) and direction cosine on (-1,1): exact in binary64
 __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 __device__ __forceinline__ double dircos(uint32_t w) { return ((double)w + 0.5) * 0x1p-31 - 1.0; }

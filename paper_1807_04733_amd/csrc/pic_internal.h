@@ -16,11 +16,13 @@ constexpr int kNC = PIC_NCOUNTERS;
 
 // Random-number purposes (fourth counter word).  One fixed slot per purpose so that a
 // branch taken or not taken never shifts the draws of another decision.
-constexpr uint32_t kTagScat = 0x000u;    // words: event, channel, new direction, split
+constexpr uint32_t kTagScat = 0x000u;    // words: (unused), channel, new direction, split
 constexpr uint32_t kTagSpawn = 0x100u;   // words: direction, spin, lineage, lineage fallback
 constexpr uint32_t kTagHalf1 = 0x200u;   // + i: i-th interface draw of the first half step
 constexpr uint32_t kTagHalf2 = 0x300u;   // + i: same for the second half step
 constexpr uint32_t kTagInject = 0x400u;  // counter (root, 0, ~0, tag): depth, dir, spin, E
+constexpr uint32_t kTagDecide = 0x500u;  // counter (lo, hi, 2m, tag): event decisions of
+                                         // steps 2m (word 0) and 2m + 1 (word 1)
 
 // Packed per-particle flags.
 constexpr uint32_t kSpinMask = 1u;

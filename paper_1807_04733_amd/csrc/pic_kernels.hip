@@ -522,11 +522,11 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         const int l = layer_of(fl);
         const LayCache c = load_lay<ET>(I, et, tau2, l, (int)(fl & kSpinMask), E);
         const double zm = z + (c.v * mu) * a.h;
-        const uint4 w = philox10(lo, hi, step0 + J, kTagScat, a.key0, a.key1);
+        const uint32_t wd = decide_word(lo, hi, step0 + J, a.key0, a.key1);
         const double x = a.dt * (inel_rate<ET>(c, tau2, E) + I.lay[l].z);
         const double ze = zm + (c.v * mu) * a.h;
         // the start lies in the layer and both half steps move the same way
-        left = u01(w.x) < x || ze > c.zhi || ze < c.zlo;
+        left = u01(wd) < x || ze > c.zhi || ze < c.zlo;
         if (!left) {
           const double zs = to_store<F>(ze);
           deposit<MODE, J>(a, I, dyn, s_edges, s_ebkt, zs, mu, E, fl, c.v, wfx, racc);
@@ -579,11 +579,10 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
                           a.key1, hc, bad);
         }
         // ---- scattering over the full step, at the mid-step state
-        const uint4 w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
         const double itel = I.lay[layer_of(fl)].z;
         const double rate = inel_rate<ET>(c, tau2, E) + itel;
         const double x = a.dt * rate;
-        const double u0 = u01(w.x);
+        const double u0 = u01(decide_word(lo, hi, step, a.key0, a.key1));
         // event iff u0 < p = 1 - exp(-x), decided without the transcendental outside a
         // sliver: x - x^2/2 < p < x, with a margin (about x^3/6) far above rounding
         bool event;
@@ -594,6 +593,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         } else {
           event = u0 < -expm1(-x);
         }
+        // the event's own words: channel (y), new direction (z), energy split (w)
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if (event) w = philox10(lo, hi, step, kTagScat, a.key0, a.key1);
         if (SCORE && event) {
           // the event's score (Eq. 2), after the channel's pending non-event terms, and the
           // channel choice's (Eqs. 5, 8); non-event terms pend again from the next step
@@ -1016,16 +1018,24 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           const long long cv = cur_val<MODE>(a, c.v, mu, rw);
           // energy bin once for both sub-steps (E does not change on the common path)
           const int eb = (a.sub_dens_on[0] || a.sub_dens_on[T - 1]) ? ebin(a, s_edges, s_ebkt, rE) : 0;
+          // the decision words of the launch's steps: one generator call per step pair
+          const uint4 wp = decide_pair((uint32_t)ru, (uint32_t)(ru >> 32), step0, a.key0, a.key1);
 #pragma unroll
           for (int j = 0; j < T; ++j) {
             if (left_at < 0) {
               const double zm = z + vmh;
-              const uint4 w = philox10((uint32_t)ru, (uint32_t)(ru >> 32), step0 + j,
-                                       kTagScat, a.key0, a.key1);
+              const uint32_t sj = step0 + (uint32_t)j;
+              uint32_t wd;
+              if (j == 0)
+                wd = (sj & 1u) ? wp.y : wp.x;
+              else if ((sj & 1u) != 0u)
+                wd = wp.y;  // same pair as step0 (step0 even)
+              else
+                wd = decide_pair((uint32_t)ru, (uint32_t)(ru >> 32), sj, a.key0, a.key1).x;
               const double ze = zm + vmh;
               // z lies in [zlo, zhi] and both half steps move it the same way, so the
               // step stays in the layer iff its end does
-              if ((double)w.x < thr || ze > c.zhi || ze < c.zlo) {
+              if ((double)wd < thr || ze > c.zhi || ze < c.zlo) {
                 left_at = j;
               } else {
                 z = to_store<F>(ze);

@@ -15,7 +15,8 @@ import numpy as np
 import workloads as W
 
 INF = float("inf")
-TAG_SCAT, TAG_SPAWN, TAG_HALF1, TAG_HALF2, TAG_INJECT = 0x000, 0x100, 0x200, 0x300, 0x400
+TAG_SCAT, TAG_SPAWN, TAG_HALF1, TAG_HALF2, TAG_INJECT, TAG_DECIDE = (
+    0x000, 0x100, 0x200, 0x300, 0x400, 0x500)
 NEVER = 0xFFFFFFFF            # u = 1 - 2^-33: no event, reflect at any T < 1
 ALWAYS = 0                    # u = 2^-33: event, transmit at any T > 2^-33
 
@@ -37,8 +38,12 @@ def test_scripted_split_absorption_and_newborn_half_step(oracle_lib):
     tau0 = 40 fs, E_min = 0.1 eV, injected at z0 = 50 nm, mu0 = 1/2 + 2^-32, spin down
     (injection word 2 ~ 1 against the pump's spin-up fraction 1/2), E0 = 1.5 eV.
 
-    Step 0: half step to z_mid = 50.25 + 2^-33; forced inelastic event (word 0 = 0); new
-      direction from word 2 = 2^30: mu1 = -1/2 + 2^-32; kept energy from word 3 = 2^31:
+    The event decisions of steps 0 and 1 are the words 0 and 1 of one counter (step
+    field 0, tag 0x500), that of step 2 word 0 of the counter with step field 2; an
+    event's own words (channel, direction, split) are words 1-3 of its step's counter
+    with tag 0.
+    Step 0: half step to z_mid = 50.25 + 2^-33; forced inelastic event (decision word 0);
+      new direction from word 2 = 2^30: mu1 = -1/2 + 2^-32; kept energy from word 3 = 2^31:
       E1 = E0/2 (Eq. 7, uniform fraction 1/2), the secondary gets E0/2 (>= E_min).  The
       spawn words give the secondary mu_c = 3/4 + 2^-32 (word 0 = 0xE0000000), spin up
       (word 1 = 0 against (1 + P0)/2 = 1/2 in Au, Eq. 19) and lineage 0x1234 (word 2).
@@ -58,13 +63,14 @@ def test_scripted_split_absorption_and_newborn_half_step(oracle_lib):
     c1, c2 = 0x1234, 0x5678
     script = [
         row((0, 0, NEVER, TAG_INJECT), (0, 0xC0000000, NEVER, 0)),
-        row((0, 0, 0, TAG_SCAT), (ALWAYS, 0, 0x40000000, 0x80000000)),
+        row((0, 0, 0, TAG_DECIDE), (ALWAYS, ALWAYS, 0, 0)),
+        row((0, 0, 0, TAG_SCAT), (0, 0, 0x40000000, 0x80000000)),
         row((0, 0, 0, TAG_SPAWN), (0xE0000000, 0, c1, 0)),
-        row((0, 0, 1, TAG_SCAT), (ALWAYS, 0, 0xFFFFFFFF, 0x10000000)),
+        row((0, 0, 1, TAG_SCAT), (0, 0, 0xFFFFFFFF, 0x10000000)),
         row((0, 0, 1, TAG_SPAWN), (0, NEVER, c2, 0)),
-        row((0, c1, 1, TAG_SCAT), (NEVER, 0, 0, 0)),
-        row((0, c1, 2, TAG_SCAT), (NEVER, 0, 0, 0)),
-        row((0, c2, 2, TAG_SCAT), (NEVER, 0, 0, 0)),
+        row((0, c1, 0, TAG_DECIDE), (0, NEVER, 0, 0)),
+        row((0, c1, 2, TAG_DECIDE), (NEVER, 0, 0, 0)),
+        row((0, c2, 2, TAG_DECIDE), (NEVER, 0, 0, 0)),
     ]
     res = oracle_lib.run(prob, records=True, script=script)
     rec = res.records
