@@ -322,6 +322,8 @@ struct LaneCounts {
 // also receives the survivors and newborns of a sub-step-0 general pass (< 64 + 64 + 128).
 constexpr int kSlowQ0 = 128;
 constexpr int kSlowQ1 = 256;
+// rounds of tiles at the end of a slab handed out on demand (the rest are interleaved)
+constexpr int kDynRounds = 16;
 
 // One launch of k_step advances every carrier of every instance by T (1 or 2) steps of the
 // Strang splitting.  A workgroup takes one slab at a time; each lane takes one carrier
@@ -350,7 +352,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   __shared__ unsigned long long s_cnt[T][kNC];
   __shared__ uint32_t s_edges[PIC_MAX_EBINS];
   __shared__ __align__(4) uint8_t s_ebkt[kEBuckets];
-  __shared__ int s_slab, s_app, s_dead;
+  __shared__ int s_slab, s_app, s_dead, s_tile;
   __shared__ unsigned long long s_fast[T], s_left[T];
 
   const int tid = threadIdx.x;
@@ -432,6 +434,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     if (tid == 0) {
       s_app = 0;
       s_dead = 0;
+      s_tile = 0;
     }
     __syncthreads();
     const DevInst& I = s_inst;
@@ -979,20 +982,36 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nfl = kDead;
       }
     };
-    fetch(wave * 64 + lane);
+    // Tiles of 64 slots: wave w streams tiles w, w + W, w + 2W, ... (W waves) up to the
+    // last kDynRounds rounds of the slab, whose tiles the waves then take in turn from a
+    // workgroup counter, so that a wave slowed down by general passes streams fewer of
+    // them and the waves reach the end of the slab together.
+    const int stat_end = total > kDynRounds * (int)blockDim.x
+                             ? (total / (int)blockDim.x - kDynRounds) * (int)blockDim.x
+                             : 0;
+    auto next_tile = [&](int cur) __attribute__((always_inline)) -> int {
+      if (cur + (int)blockDim.x < stat_end) return cur + (int)blockDim.x;
+      int v = 0;
+      if (lane == 0) v = stat_end + atomicAdd(&s_tile, 64);
+      return __builtin_amdgcn_readfirstlane(v);
+    };
+    int tb = wave * 64 < stat_end ? wave * 64 : next_tile(stat_end);
+    fetch(tb + lane);
     // Each iteration streams 64 slots (each lane adds at most one entry to one queue),
     // then runs the general path on full queues; past the end it empties the queues.  The
     // sub-step-1 queue then holds < 64 + 64 + 128 entries.
-    for (int tb = wave * 64;; tb += blockDim.x) {
+    for (;;) {
       const bool streaming = tb < total;
       if (!streaming && sn0 == 0 && sn1 == 0) break;
+      int tb_next = tb;
       if (streaming) {
         const int t = tb + lane;
         const F rz = nz, rmu = nmu;
         const uint32_t rE = nE, rfl = nfl;
         const uint64_t ru = nu;
         const double rr = nr;
-        fetch(t + (int)blockDim.x);
+        tb_next = next_tile(tb);
+        fetch(tb_next + lane);
         // the weight is read for the current tile only (not prefetched): one register less
         // held across the iteration
         const uint32_t rw = WT && t < tail0 ? at(sp.w, (uint32_t)t) : kW1;
@@ -1070,6 +1089,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       }
       if constexpr (T > 1)
         while (sn1 >= need) drain_last(sn1 < 64 ? sn1 : 64);
+      tb = tb_next;
     }
 #pragma unroll
     for (int j = 0; j < T; ++j) {
