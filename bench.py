@@ -155,7 +155,7 @@ def cpu_baseline(prob, roots: int):
                        f"{ps} particle-steps, {dt:.1f} s wall)")
 
 
-def adjoint_leg(n_primaries: int, tune_steps: int):
+def adjoint_leg(n_primaries: int, tune_steps: int, slab: int = 8192):
     """Plain single-instance forward and its causal adjoint on the Fe(15)/Au(80) bilayer
     (E0 ~ U(0.5, 2) eV, 400 x 1 fs): loss = L2 distance of the spin current at z = 80 nm
     to a target curve; the adjoint returns 8 gradients (4 tau0, 4 T)."""
@@ -164,8 +164,9 @@ def adjoint_leg(n_primaries: int, tune_steps: int):
 
     prob = W.config3(n_primaries=n_primaries)
     # the replay keeps every carrier ever created (7.3 per primary on average at this
-    # workload, at most 20 per tree): 10 slots per primary over 8192-primary slabs
-    sim = PicSim(prob, device="cuda:0", adjoint=1, slab_primaries=8192, capacity_factor=10)
+    # workload, at most 20 per tree): 10 slots per primary over slabs of thousands of
+    # primaries
+    sim = PicSim(prob, device="cuda:0", adjoint=1, slab_primaries=slab, capacity_factor=10)
     if tune_steps > 0:
         sim.autotune(trial_steps=tune_steps)
     sim.step()
@@ -431,6 +432,8 @@ def main():
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--tuning", default="", help="JSON dict of launch tuning")
     ap.add_argument("--slab", type=int, default=0)
+    ap.add_argument("--adjoint-slab", type=int, default=8192,
+                    help="primaries per slab of the forward+adjoint leg (0: the default)")
     ap.add_argument("--tune-steps", type=int, default=60,
                     help="steps per autotuning trial (0: keep the default launch shape)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -599,7 +602,8 @@ def main():
     if args.adjoint_primaries > 0:
         print("[bench] forward + adjoint leg", file=sys.stderr, flush=True)
         try:
-            extra["adjoint"] = adjoint_leg(args.adjoint_primaries, args.tune_steps)
+            extra["adjoint"] = adjoint_leg(args.adjoint_primaries, args.tune_steps,
+                                           args.adjoint_slab)
         except Exception as e:  # reported, never hidden
             extra["adjoint"] = {"error": str(e)}
         print(f"[bench] adjoint: {extra['adjoint']}", file=sys.stderr, flush=True)

@@ -148,8 +148,12 @@ typedef struct {
   int32_t  n_ebins;                         /* 1..PIC_MAX_EBINS */
   uint32_t e_edges[PIC_MAX_EBINS];          /* increasing lower edges (last bin open) */
   int32_t  dens_stride, cur_stride;         /* deposit every k-th step (slot n/k) */
-  int32_t  slab_primaries;                  /* primaries per slab; 0 = 16384, or fewer
-                                               so that there are >= 2048 slabs */
+  int32_t  slab_primaries;                  /* primaries per slab; 0 = default: with
+                                               instances of equal size, a slab count that
+                                               is a multiple of the step kernel's resident
+                                               workgroups (2 per CU; 4 with an adjoint) at
+                                               <= 32768 primaries per slab; else 16384, or
+                                               fewer so that there are >= 2048 slabs */
   double   capacity_factor;                 /* slots per primary; 0 = floor(E0max/Emin)+2 */
   int32_t  adjoint;                         /* workspace for pic_backward: 0 none, 1 causal
                                                (K <= 16), 2 whole-tree, 3 both.  Needs equal

@@ -170,18 +170,46 @@ double default_capacity(const pic_config* c, const pic_instance& I) {
   return std::min<double>((c->flags & PIC_F_ABSORB_NEXT) ? 2.0 * f : f, 64.0);
 }
 
+// Workgroups of the step kernel's default launch shape that run at once on the device
+// (two 512-thread workgroups per CU).
+int64_t resident_step_workgroups() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return 2 * (int64_t)cus;
+}
+
+// Default primaries per slab.  Instances of equal size give slabs of about equal work: their
+// slab count is then a multiple of the workgroups that run at once (twice that with an
+// adjoint, whose one-step replay runs four 256-thread workgroups per CU), so that each
+// workgroup takes as many slabs as the others, with at most 32768 primaries per slab (one
+// slab per workgroup where that suffices: the spin valve's launch measured 0.48 ms against
+// 0.50 with two slabs per workgroup and 0.53 with four).  Otherwise 16384 primaries (fewer
+// slab and instance switches per workgroup), smaller when the problem would give fewer
+// than 2048 slabs, which the work-ordered slab queue balances over the workgroups.
+int default_slab_primaries(const pic_config* c, int64_t total) {
+  bool uniform = c->n_instances > 0;
+  for (int i = 1; i < c->n_instances; ++i)
+    uniform = uniform && c->inst[i].n_primaries == c->inst[0].n_primaries;
+  const int64_t R = resident_step_workgroups() * (c->adjoint ? 2 : 1);
+  if (uniform && R % c->n_instances == 0) {
+    const int64_t k = std::max<int64_t>(1, (total + R * 32768 - 1) / (R * 32768));
+    const int64_t S = R * k / c->n_instances;  // slabs per instance
+    const int64_t N = c->inst[0].n_primaries;
+    return (int)std::max<int64_t>(256, (N + S - 1) / S);
+  }
+  return (int)std::min<int64_t>(16384, std::max<int64_t>(256, (total + 2047) / 2048));
+}
+
 Plan make_plan(const pic_config* c) {
   Plan p;
   p.state_bytes = (c->flags & PIC_F_STATE_FP64) ? 8 : 4;
   p.debug = (c->flags & PIC_F_DEBUG) != 0;
-  // default slab size: 16384 primaries (fewer slab and instance switches per workgroup),
-  // smaller when the problem would then give fewer than 2048 slabs (every workgroup of a
-  // launch needs work)
   int64_t total = 0;
   for (int i = 0; i < c->n_instances; ++i) total += c->inst[i].n_primaries;
-  const int P = c->slab_primaries > 0
-                    ? c->slab_primaries
-                    : (int)std::min<int64_t>(16384, std::max<int64_t>(256, (total + 2047) / 2048));
+  const int P = c->slab_primaries > 0 ? c->slab_primaries : default_slab_primaries(c, total);
   p.n_dslots = (c->n_steps + c->dens_stride - 1) / c->dens_stride;
   p.n_cslots = (c->n_steps + c->cur_stride - 1) / c->cur_stride;
   // Slabs are handed out in the order of the slab table, so the instances are laid out
