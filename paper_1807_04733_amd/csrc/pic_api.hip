@@ -182,8 +182,8 @@ int64_t resident_step_workgroups() {
 }
 
 // Default primaries per slab.  Instances of equal size give slabs of about equal work: their
-// slab count is then a multiple of the workgroups that run at once (twice that with an
-// adjoint, whose one-step replay runs four 256-thread workgroups per CU), so that each
+// slab count is then a multiple of the workgroups that run at once (twice that where the
+// adjoint uses the one-step replay, which runs four 256-thread workgroups per CU), so that each
 // workgroup takes as many slabs as the others, with at most 32768 primaries per slab (one
 // slab per workgroup where that suffices: the spin valve's launch measured 0.48 ms against
 // 0.50 with two slabs per workgroup and 0.53 with four).  Otherwise 16384 primaries (fewer
@@ -193,7 +193,13 @@ int default_slab_primaries(const pic_config* c, int64_t total) {
   bool uniform = c->n_instances > 0;
   for (int i = 1; i < c->n_instances; ++i)
     uniform = uniform && c->inst[i].n_primaries == c->inst[0].n_primaries;
-  const int64_t R = resident_step_workgroups() * (c->adjoint ? 2 : 1);
+  // the one-step replay: the causal estimator, and the whole tree with energy tables,
+  // weights or debug counts (otherwise the step kernel replays the whole tree)
+  bool tables = false;
+  for (int i = 0; i < c->n_instances; ++i) tables = tables || c->inst[i].e_nodes > 0;
+  const bool replay = (c->adjoint & 1) ||
+                      ((c->adjoint & 2) && (tables || (c->flags & (PIC_F_WEIGHTS | PIC_F_DEBUG))));
+  const int64_t R = resident_step_workgroups() * (replay ? 2 : 1);
   if (uniform && R % c->n_instances == 0) {
     const int64_t k = std::max<int64_t>(1, (total + R * 32768 - 1) / (R * 32768));
     const int64_t S = R * k / c->n_instances;  // slabs per instance
