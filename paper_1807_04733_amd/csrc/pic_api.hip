@@ -1025,7 +1025,7 @@ pic_status pic_layout_of(const pic_ctx* c, pic_layout* o) {
   o->state_bytes = p.state_bytes;
   o->flags_spin_shift = 0;
   o->flags_layer_shift = kLayerShift;
-  o->flags_layer_bits = 4;
+  o->flags_layer_bits = __builtin_popcount(kLayerMask);
   o->flags_gen_shift = kGenShift;
   o->flags_dead_bit = kDead;
   o->off_w = p.off_w;

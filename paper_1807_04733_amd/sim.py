@@ -367,8 +367,9 @@ class PicSim:
         uid = arr(lay.off_uid, cap, torch.int64)[ti].cpu().numpy().view(np.uint64)
         fl = arr(lay.off_flags, cap, torch.int32)[ti].cpu().numpy().view(np.uint32)
         out = dict(z=z, mu=mu, E=E, uid=uid,
-                   spin=(fl & 1).astype(np.int32),
-                   layer=((fl >> np.uint32(lay.flags_layer_shift)) & np.uint32(0xF)).astype(np.int32),
+                   spin=((fl >> np.uint32(lay.flags_spin_shift)) & np.uint32(1)).astype(np.int32),
+                   layer=((fl >> np.uint32(lay.flags_layer_shift)) &
+                          np.uint32((1 << lay.flags_layer_bits) - 1)).astype(np.int32),
                    gen=((fl >> np.uint32(lay.flags_gen_shift)) & np.uint32(0xFF)).astype(np.int32),
                    dead=((fl & np.uint32(lay.flags_dead_bit)) != 0),
                    inst=inst[slab_of].astype(np.int32))
