@@ -14,8 +14,10 @@
  *   - A channel is (material, spin local to the layer); ch_of[l][s] selects the channel
  *     of layer l for global spin s.  Interface k lies between layers k and k+1;
  *     tt_of[k][d][s] is the transmission table for direction d (0: +z, 1: -z).
- *   - Random numbers: Philox4x32-10 keyed by `seed`, counter (uid_lo, uid_hi, step, tag);
- *     results are a pure function of the inputs, independent of launch configuration.
+ *   - Random numbers: Philox4x32-10 keyed by `seed`, counter (uid_lo, uid_hi, step, tag),
+ *     one tag per purpose; the event decisions of steps 2m and 2m+1 are words 0 and 1 of
+ *     the counter with step field 2m.  Results are a pure function of the inputs,
+ *     independent of launch configuration.
  *
  * Memory and streams
  *   - The library never allocates device memory.  The caller supplies one device
