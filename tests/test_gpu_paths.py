@@ -170,3 +170,44 @@ def test_slab_dead_count_is_exact(torch_gpu, oracle_mod):
             with pytest.raises(Exception):
                 sim.counters()               # slots ran out: reported, nothing written beyond
         sim.close()
+
+
+def test_default_slabs_follow_the_resident_workgroups(torch_gpu, oracle_mod):
+    """Default slab size: instances of equal size get a slab count that is a multiple of
+    the step kernel's resident workgroups (2 per CU); instances of different sizes get
+    slabs of at most 16384 primaries.  Results stay the oracle's either way."""
+    import torch
+    from paper_1807_04733_amd import PicSim
+    R = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    one = W.config1(parallel=True, n_primaries=2_000_000, n_steps=2)
+    sim = PicSim(one)
+    _say(f"[slabs] one instance of 2e6 primaries: {sim.layout.n_slabs} slabs (R = {R})")
+    assert sim.layout.n_slabs % R == 0
+    sim.close()
+    # equal instances: a multiple of R over all of them
+    prob = W.config1(parallel=True, n_primaries=4000, n_steps=40)
+    its = [prob.instances[0], W.make_instance(W.spin_valve(parallel=False), n_primaries=4000,
+                                              n_steps=40, e0_ev=(0.5, 0.5), e_span_ev=(1.5, 1.5))]
+    prob.instances = W.with_root_offsets(its)
+    sim = PicSim(prob)
+    n = sim.layout.n_slabs
+    sim.step()
+    dens, cur = sim.int_bins()
+    cnt = sim.counters()
+    sim.close()
+    ref = oracle_mod.run(prob)
+    _say(f"[slabs] two equal instances of 4000 primaries: {n} slabs")
+    assert n == 2 * -(-4000 // 256)  # 256 primaries per slab at least
+    for i in range(2):
+        assert np.array_equal(dens[i], ref.dens[i]) and np.array_equal(cur[i], ref.cur[i])
+    assert np.array_equal(cnt, ref.counters)
+    # different sizes: at most 16384 primaries per slab
+    big = W.config1(parallel=True, n_primaries=100_000, n_steps=2)
+    its = [big.instances[0], W.make_instance(W.spin_valve(parallel=False), n_primaries=50_000,
+                                             n_steps=2, e0_ev=(0.5, 0.5), e_span_ev=(1.5, 1.5))]
+    big.instances = W.with_root_offsets(its)
+    sim = PicSim(big)
+    _say(f"[slabs] 1e5 + 5e4 primaries: {sim.layout.n_slabs} slabs")
+    # 150000 / 2048 primaries per slab rounds up to the minimum of 256
+    assert sim.layout.n_slabs == -(-100_000 // 256) + -(-50_000 // 256)
+    sim.close()
