@@ -445,7 +445,12 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
   const size_t stat = step_static_lds();
   const bool stage = stage_end + stat <= per_wg && stage_end <= c->max_lds;
   if (a) a->lds_stage_at = stage ? (int32_t)stage_at : -1;
-  return stage ? stage_end : off;
+  // and of the first entries of the sub-step-1 queue behind them, where those fit too
+  const size_t stage1_end =
+      stage_end + (size_t)(block / 64) * stage1_wave_bytes(c->plan.state_bytes == 8);
+  const bool stage1 = stage && n_sub > 1 && stage1_end + stat <= per_wg && stage1_end <= c->max_lds;
+  if (a) a->lds_stage1_at = stage1 ? (int32_t)stage_end : -1;
+  return stage1 ? stage1_end : stage ? stage_end : off;
 }
 
 // LDS of a one-step launch that deposits both moments (the largest one-step layout).
@@ -503,6 +508,7 @@ StepArgs step_args(const pic_ctx* c, int n) {
   a.wt = c->at<uint32_t>(p.off_w);
   a.lds_etab_at = -1;
   a.lds_stage_at = -1;
+  a.lds_stage1_at = -1;
   a.n_slabs = (int32_t)p.slab_inst.size();
   a.n_inst = c->cfg.n_instances;
   a.n_ebins = c->cfg.n_ebins;

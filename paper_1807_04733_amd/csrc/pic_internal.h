@@ -148,6 +148,9 @@ struct StepArgs {
   // per-wave copies of the state of the carriers in the sub-step-0 queue (stage_wave_bytes
   // per wave), so that their general pass reads LDS instead of HBM; -1: not staged
   int32_t lds_stage_at;
+  // per-wave copies of the state of the first kStage1 entries of the sub-step-1 queue
+  // (stage1_wave_bytes per wave); -1: not staged
+  int32_t lds_stage1_at;
   // The two passes of the whole-tree adjoint run by the step kernel itself (modes
   // kModeRet, kModeScore of pic_kernels.hip), with the forward's launch structure:
   // per-slot partial returns, per-root returns, dL/d(density), dL/d(current) (pass 1
@@ -204,6 +207,9 @@ constexpr size_t step_queue_bytes(int n_sub) {
 // bytes per wave of the staged sub-step-0 queue: z and cos(theta) (binary32 or binary64),
 // E, flags and uid of each of its 128 entries
 constexpr size_t stage_wave_bytes(bool fp64) { return 128 * ((fp64 ? 16 : 8) + 16); }
+// the same for the first kStage1 entries of the sub-step-1 queue (two-step launches)
+constexpr int kStage1 = 64;
+constexpr size_t stage1_wave_bytes(bool fp64) { return kStage1 * ((fp64 ? 16 : 8) + 16); }
 
 // Launch shape of one step.
 struct StepLaunch {

@@ -388,6 +388,14 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
   uint32_t* const st_E = (uint32_t*)(st_mu + kSlowQ0);
   uint32_t* const st_fl = st_E + kSlowQ0;
   uint64_t* const st_u = (uint64_t*)(st_fl + kSlowQ0);
+  // the same for the first kStage1 entries of the sub-step-1 queue (when staged)
+  const bool STG1 = T > 1 && a.lds_stage1_at >= 0;
+  F* const s1_z = (F*)(dyn + (STG1 ? a.lds_stage1_at : 0) +
+                       (size_t)wave * stage1_wave_bytes(sizeof(F) == 8));
+  F* const s1_mu = s1_z + kStage1;
+  uint32_t* const s1_E = (uint32_t*)(s1_mu + kStage1);
+  uint32_t* const s1_fl = s1_E + kStage1;
+  uint64_t* const s1_u = (uint64_t*)(s1_fl + kStage1);
   static_assert(sizeof(ChildQueue) == kChildQueueBytes, "queue layout");
   const double* const et = ET ? (const double*)(dyn + a.lds_etab_at) : nullptr;
   const bool tau2 = a.tau_exp2 != 0;
@@ -500,15 +508,28 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         sn0 += __popcll(m);
       }
     };
-    // ---- put the slots of the lanes with `pred` into the queue of sub-step J >= 1
-    auto push = [&](auto sub, bool pred, uint32_t slot) __attribute__((always_inline)) {
+    // ---- put the slots of the lanes with `pred` into the queue of sub-step J >= 1, with a
+    // copy of their stored state (z, cos(theta), E, flags, uid) for the first entries when
+    // those are staged
+    auto push = [&](auto sub, bool pred, uint32_t slot, F z, F mu, uint32_t E, uint32_t fl,
+                    uint64_t u) __attribute__((always_inline)) {
       constexpr int J = decltype(sub)::value;
       static_assert(J > 0, "sub-step 0 entries go through push0");
       const uint64_t m = __ballot(pred);
       if (m) {
-        if (pred) SQ1[sn1 + prefix_count(m)] = slot;
+        if (pred) {
+          const int q = sn1 + prefix_count(m);
+          SQ1[q] = slot;
+          if (STG1 && q < kStage1) {
+            s1_z[q] = z;
+            s1_mu[q] = mu;
+            s1_E[q] = E;
+            s1_fl[q] = fl;
+            s1_u[q] = u;
+          }
+          n_left[J] += 1;
+        }
         sn1 += __popcll(m);
-        if (pred) n_left[J] += 1;
       }
     };
 
@@ -542,7 +563,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           if (RET && racc != r_in) at(sp.r, slot) = racc;
         }
       }
-      push(sub, left, slot);
+      push(sub, left, slot, (F)z, (F)mu, E, fl, ((uint64_t)hi << 32) | lo);
     };
 
     // ---------------------------------------------------------------- general path
@@ -815,10 +836,14 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
     };
 
     // re-read the top n slots of a sub-step's queue and bring z to the start of that step
-    auto pop_state = [&](uint32_t* SQ, int& sn, int n, int phase, bool staged, uint32_t& g,
-                         double& z, double& mu, uint32_t& E, uint32_t& fl, uint32_t& lo,
-                         uint32_t& hi, uint64_t& evp, uint32_t& wfx, double& racc)
-                         __attribute__((always_inline)) -> bool {
+    // Pop the top n entries of the queue of sub-step Q (0 or 1) with their stored state:
+    // from the queue's LDS copies where they are staged (every entry of the sub-step-0
+    // queue, the first kStage1 of the sub-step-1 queue), else from the particle arrays.
+    auto pop_state = [&](auto which, uint32_t* SQ, int& sn, int n, int phase, bool staged,
+                         uint32_t& g, double& z, double& mu, uint32_t& E, uint32_t& fl,
+                         uint32_t& lo, uint32_t& hi, uint64_t& evp, uint32_t& wfx,
+                         double& racc) __attribute__((always_inline)) -> bool {
+      constexpr int Q = decltype(which)::value;
       wave_sync();
       const bool act = lane < n;
       const int q = sn - n + lane;
@@ -828,19 +853,20 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       F sz = 0, smu = 0;
       uint32_t sE = 0, sfl = kDead;
       uint64_t su = 0;
-      if (staged && act) {
-        sz = st_z[q];
-        smu = st_mu[q];
-        sE = st_E[q];
-        sfl = st_fl[q];
-        su = st_u[q];
+      const bool stg = staged && act && (Q == 0 || q < kStage1);
+      if (stg) {
+        sz = Q == 0 ? st_z[q] : s1_z[q];
+        smu = Q == 0 ? st_mu[q] : s1_mu[q];
+        sE = Q == 0 ? st_E[q] : s1_E[q];
+        sfl = Q == 0 ? st_fl[q] : s1_fl[q];
+        su = Q == 0 ? st_u[q] : s1_u[q];
       }
       sn -= n;
       wave_sync();
       fl = kDead;
       if (act) {
         uint64_t u;
-        if (staged) {
+        if (stg) {
           fl = sfl;
           z = (double)sz;
           mu = (double)smu;
@@ -873,9 +899,9 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
       double z = 0.0, mu = 0.0, racc = 0.0;
       uint64_t evp = 0;
-      const bool act = pop_state(T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
-                                 a.sub_z_phase[T - 1], T == 1 && STG, g, z, mu, E, fl, lo, hi,
-                                 evp, wfx, racc);
+      const bool act = pop_state(Sub<T - 1>{}, T > 1 ? SQ1 : SQ0, T > 1 ? sn1 : sn0, n,
+                                 a.sub_z_phase[T - 1], T > 1 ? STG1 : STG, g, z, mu, E, fl, lo,
+                                 hi, evp, wfx, racc);
       general(Sub<T - 1>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot, racc);
       drain_kids(Sub<T - 1>{});
     };
@@ -886,8 +912,8 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         uint32_t g = 0, E = 0, fl = kDead, lo = 0, hi = 0, slot = 0, wfx = kW1;
         double z = 0.0, mu = 0.0, racc = 0.0;
         uint64_t evp = 0;
-        const bool act = pop_state(SQ0, sn0, n, a.sub_z_phase[0], STG, g, z, mu, E, fl, lo, hi,
-                                   evp, wfx, racc);
+        const bool act = pop_state(Sub<0>{}, SQ0, sn0, n, a.sub_z_phase[0], STG, g, z, mu, E,
+                                   fl, lo, hi, evp, wfx, racc);
         const bool surv =
             general(Sub<0>{}, act, false, g, z, mu, E, fl, lo, hi, evp, wfx, slot, racc);
         cont(Sub<1>{}, surv, slot, z, mu, E, fl, lo, hi, wfx, racc);
@@ -959,7 +985,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
       if constexpr (J == 0)
         push0(placed, pos, qz, qmu, qE, qfl, qu);
       else
-        push(sub, placed, pos);
+        push(sub, placed, pos, qz, qmu, qE, qfl, qu);
     };
 
     // The slot a lane will handle in its next iteration is fetched one iteration ahead,
@@ -1075,7 +1101,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           if (RET && left_at != 0 && racc != rr) at(sp.r, gi) = racc;
         }
         push0(left_at == 0, gi, rz, rmu, rE, rfl, ru);
-        if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi);
+        if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi, rz, rmu, rE, rfl, ru);
         // ---- new primaries of each sub-step
         inject(Sub<0>{}, is_new0, f00, t - tail0);
         if constexpr (T > 1) inject(Sub<1>{}, is_new1, f01, t - tail0 - n_inj0);
