@@ -568,8 +568,9 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n, int adj_pass = 0,
   int grid = c->tune.grid > 0 ? c->tune.grid : 512;
   grid = std::max(1, std::min(grid, n_slabs));
   const int T = std::max(1, std::min(c->tune.sub_steps, kMaxSub));
-  // write-back period: a multiple of the steps per launch
-  int K = std::max(1, std::min(c->tune.z_every, kMaxZEvery));
+  // write-back period: a multiple of the steps per launch; the adjoint passes, which move
+  // more bytes per carrier than the forward, store z as rarely as the stamps allow
+  int K = std::max(1, std::min(adj_pass ? kMaxZEvery : c->tune.z_every, kMaxZEvery));
   K = std::min(kMaxZEvery / T * T, (K + T - 1) / T * T);
   for (int s = start; s < start + n;) {
     // launches of T steps, aligned to the call's start; the write-back periods are

@@ -1003,7 +1003,10 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nmu = at(sp.mu, g);
         nE = at(sp.E, g);
         nu = at(sp.uid, g);
-        if (RET) nr = at(sp.r, g);
+        // adjoint pass 1: the partial returns are read and written once per launch, with
+        // the non-temporal hint, so that they pass through the caches without displacing
+        // what is re-read (with plain accesses the pass takes 3 % longer)
+        if (RET) nr = __builtin_nontemporal_load(&at(sp.r, g));
       } else {
         nfl = kDead;
       }
@@ -1098,7 +1101,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
           }
           // adjoint pass 1: the return of the common steps, stored before a general pass
           // of sub-step 1 re-reads it
-          if (RET && left_at != 0 && racc != rr) at(sp.r, gi) = racc;
+          if (RET && left_at != 0 && racc != rr) __builtin_nontemporal_store(racc, &at(sp.r, gi));
         }
         push0(left_at == 0, gi, rz, rmu, rE, rfl, ru);
         if constexpr (T > 1) push(Sub<1>{}, left_at == 1, gi, rz, rmu, rE, rfl, ru);
@@ -1168,13 +1171,15 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
 // dead slots below L and live slots at or above L into two LDS rings, kScanTile slots per
 // scan round, and moves them in pairs.  Sources and destinations lie on either side of L,
 // so the moves need no ordering among themselves; the two counts are equal, so every dead
-// slot below L is filled.
-constexpr int kCompactBlock = 256;
-constexpr int kCompactPer = 4;                                // slots per thread per round
+// slot below L is filled.  The widest workgroup does it fastest: 1024 threads with two
+// slots each per round took 21.6 ms per batched run and 5.3 ms per spin-valve run against
+// 23.6 and 6.2 ms with 256 threads and four slots each.
+constexpr int kCompactBlock = 1024;
+constexpr int kCompactPer = 2;                                // slots per thread per round
 constexpr int kScanTile = kCompactBlock * kCompactPer;
 constexpr int kHoleBatch = 1024;                              // dead slots per move batch
-constexpr int kRingH = 2048;                                  // > kHoleBatch - 1 + kScanTile
-constexpr int kRingT = 4096;                                  // > kRingH - 1 + kScanTile
+constexpr int kRingH = 4096;                                  // > kHoleBatch - 1 + kScanTile
+constexpr int kRingT = 8192;                                  // > kRingH - 1 + kScanTile
 static_assert(kHoleBatch - 1 + kScanTile <= kRingH && kRingH - 1 + kScanTile <= kRingT,
               "ring bounds");
 
