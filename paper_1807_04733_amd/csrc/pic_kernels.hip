@@ -1005,7 +1005,7 @@ __global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
         nu = at(sp.uid, g);
         // adjoint pass 1: the partial returns are read and written once per launch, with
         // the non-temporal hint, so that they pass through the caches without displacing
-        // what is re-read (with plain accesses the pass takes 3 % longer)
+        // what is re-read (with plain accesses the pass takes about 4 % longer)
         if (RET) nr = __builtin_nontemporal_load(&at(sp.r, g));
       } else {
         nfl = kDead;
