@@ -18,6 +18,7 @@ import json
 import os
 import sys
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -201,18 +202,19 @@ def adjoint_leg(n_primaries: int, tune_steps: int, slab: int = 8192):
                 tuning=tuning, grad=[float(x) for x in grad])
 
 
-def multilayer_adjoint_leg(n_instances: int, tune_steps: int):
+def multilayer_adjoint_leg(n_instances: int, tune_steps: int, tuning: Optional[dict] = None):
     """[Fe(10)/Au(30)]x5 multilayers, a 50 fs Gaussian pump (3.125e6 primaries per stack),
     T(E) tables of 64 nodes, 2000 x 0.5 fs: the forward run and its whole-tree adjoint over
     260 parameters (ln tau0 of 4 channels, 4 tables x 64 nodes).  Loss: L2 distance of the
     spin current over every (t, z) to a target curve (0.9 times the run's own).  By default
-    8 stacks, one GPU's share of the 64-stack workload sharded over 8 GPUs by stack."""
+    8 stacks, one GPU's share of the 64-stack workload sharded over 8 GPUs by stack.  A
+    given `tuning` replaces the autotuner (a fixed launch shape for profiling)."""
     import torch
     from paper_1807_04733_amd import PicSim
 
     prob = W.config4(n_instances=n_instances)
-    sim = PicSim(prob, device="cuda:0", adjoint=2)
-    if tune_steps > 0:
+    sim = PicSim(prob, device="cuda:0", adjoint=2, tuning=tuning)
+    if tuning is None and tune_steps > 0:
         # the pump peaks at step 200: tune on a prefix that holds most of it
         sim.autotune(trial_steps=max(tune_steps, 250))
     sim.step()
@@ -411,6 +413,17 @@ def summarize_pmc(path: str, last: int):
     print(f"step-kernel dispatches averaged: {len(sel)} (of {len(steps)})")
     for c in counters if sel else []:
         print(f"  {c}: {sum(per[d][c] for d in sel) / len(sel):.6g} per dispatch")
+    # with several step-kernel instantiations (the forward and the adjoint passes): each
+    # one over its own last `last` dispatches
+    names = sorted({name[d] for d in steps})
+    for k in names if len(names) > 1 else []:
+        ds = [d for d in steps if name[d] == k]
+        ds = ds[-last:] if last else ds
+        for c in counters:
+            vals = [per[d][c] for d in ds if c in per[d]]
+            if vals:
+                print(f"  [{k[:48]}] {c}: {sum(vals) / len(vals):.6g} per dispatch "
+                      f"(last {len(vals)} of {sum(1 for d in steps if name[d] == k)})")
     for k in sorted(set(name.values())):
         if "k_step" in k:
             continue
@@ -481,7 +494,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4}))
         return
     if args.multilayer_only:
-        print(json.dumps(multilayer_adjoint_leg(args.multilayer_instances, args.tune_steps)))
+        print(json.dumps(multilayer_adjoint_leg(args.multilayer_instances, args.tune_steps,
+                                                json.loads(args.tuning) if args.tuning else None)))
         return
     if args.gpus != 1:
         print("this build runs on one GPU only: the particle update is sharded across GPUs "
