@@ -339,16 +339,20 @@ def summarize_trace(path: str):
     return None
 
 
+# the step kernel and the host code that plans its launches (LDS layout, queue copies,
+# 16-bit density slices, steps per launch), which changes what a launch does
 KERNEL_SOURCES = ("paper_1807_04733_amd/csrc/pic_kernels.hip",
                   "paper_1807_04733_amd/csrc/pic_device.h",
-                  "paper_1807_04733_amd/csrc/pic_internal.h")
+                  "paper_1807_04733_amd/csrc/pic_internal.h",
+                  "paper_1807_04733_amd/csrc/pic_api.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_hbm_traffic.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_step_batched_256_sq_counters.md")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the step kernel's code: its source files with // comments and blank lines
-    removed, so that a comment edit does not disown a counter summary."""
+    """Hash of the step kernel's code and of its launch planning: the source files with //
+    comments and blank lines removed, so that a comment edit does not disown a counter
+    summary."""
     import hashlib
     import re
 

@@ -445,11 +445,13 @@ size_t step_layout(const pic_ctx* c, int block, int n_sub, const int* dens_on, c
   const size_t stat = step_static_lds();
   const bool stage = stage_end + stat <= per_wg && stage_end <= c->max_lds;
   if (a) a->lds_stage_at = stage ? (int32_t)stage_at : -1;
-  // and of the first entries of the sub-step-1 queue behind them, where those fit too
+  // and of the first entries of the sub-step-1 queue behind them (or in their place when
+  // they do not fit), where those fit
+  const size_t stage1_at = stage ? stage_end : stage_at;
   const size_t stage1_end =
-      stage_end + (size_t)(block / 64) * stage1_wave_bytes(c->plan.state_bytes == 8);
-  const bool stage1 = stage && n_sub > 1 && stage1_end + stat <= per_wg && stage1_end <= c->max_lds;
-  if (a) a->lds_stage1_at = stage1 ? (int32_t)stage_end : -1;
+      stage1_at + (size_t)(block / 64) * stage1_wave_bytes(c->plan.state_bytes == 8);
+  const bool stage1 = n_sub > 1 && stage1_end + stat <= per_wg && stage1_end <= c->max_lds;
+  if (a) a->lds_stage1_at = stage1 ? (int32_t)stage1_at : -1;
   return stage1 ? stage1_end : stage ? stage_end : off;
 }
 
@@ -593,14 +595,24 @@ pic_status enqueue_steps(pic_ctx* c, int start, int n, int adj_pass = 0,
       dens_on[j] = j < ns && (sj % c->cfg.dens_stride) == 0;
       cur_on[j] = j < ns && (sj % c->cfg.cur_stride) == 0;
     }
-    // Two density slices of 32-bit counters that would cost a workgroup per CU are held as
-    // 16-bit counters (unweighted runs without energy tables; the counts stay exact).
+    // Density slices are held as 16-bit counters (unweighted runs without energy tables;
+    // the counts stay exact) where two 32-bit slices would cost a workgroup per CU, or where
+    // one 32-bit slice leaves no room for copies of queued carriers that a 16-bit one does.
     bool dens16 = false;
-    if (adj_pass == 0 && ns > 1 && dens_on[0] && dens_on[1] && c->dens_lds && c->plan.off_w < 0 &&
-        c->plan.etab_max == 0 &&
-        step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) + step_static_lds() >
-            lds_per_wg(c->tune.block))
-      dens16 = true;
+    if (adj_pass == 0 && ns > 1 && (dens_on[0] || dens_on[1]) && c->dens_lds &&
+        c->plan.off_w < 0 && c->plan.etab_max == 0) {
+      if (dens_on[0] && dens_on[1]) {
+        dens16 = step_layout(c, c->tune.block, ns, dens_on, cur_on, nullptr) + step_static_lds() >
+                 lds_per_wg(c->tune.block);
+      } else {
+        StepArgs l32 = a, l16 = a;
+        step_layout(c, c->tune.block, ns, dens_on, cur_on, &l32, false);
+        step_layout(c, c->tune.block, ns, dens_on, cur_on, &l16, true);
+        const int copies32 = (l32.lds_stage_at >= 0) + (l32.lds_stage1_at >= 0);
+        const int copies16 = (l16.lds_stage_at >= 0) + (l16.lds_stage1_at >= 0);
+        dens16 = copies16 > copies32;
+      }
+    }
     // one step at a time where two density slices do not fit next to each other, or where
     // the first step would have to store z
     const bool first_writes = (s - start) % K == K - 1 || s == start + n - 1;
