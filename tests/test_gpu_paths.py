@@ -211,3 +211,31 @@ def test_default_slabs_follow_the_resident_workgroups(torch_gpu, oracle_mod):
     # 150000 / 2048 primaries per slab rounds up to the minimum of 256
     assert sim.layout.n_slabs == -(-100_000 // 256) + -(-50_000 // 256)
     sim.close()
+
+
+@pytest.mark.parametrize("n_ebins", [48, 52])
+def test_single_density_slice_as_16_bit_counters(torch_gpu, oracle_mod, n_ebins):
+    """Two-step launches with one density slice (density every third step) on 100 depth x
+    n_ebins energy bins: a 32-bit slice (38.4 or 41.6 KB) fits next to the current slices
+    and the queues of a 512-thread workgroup but leaves no room for copies of queued
+    carriers, a 16-bit one does (the sub-step-0 copies with 48 bins, only the sub-step-1
+    head with 52), so these launches take 16-bit counters and the copies.  Counters and
+    int64 bins equal the oracle's exactly."""
+    layers = [W.Layer("Fe", 10.0, +1), W.Layer("Au", 90.0, 0)]
+    inst = W.make_instance(layers, n_primaries=20_000, n_steps=12, e0_ev=(0.8, 2.0),
+                           e_span_ev=(1.0, 0.0))
+    prob = W.Problem([inst], seed=5, dt=1.0, n_steps=12, dens_stride=3,
+                     e_edges=W.energy_edges(2.0 / n_ebins, 2.0), name=f"one_slice_{n_ebins}")
+    assert inst.nz == 100 and prob.n_ebins == n_ebins
+    from paper_1807_04733_amd import PicSim
+    sim = PicSim(prob, tuning={"block": 512, "grid": 64, "sub_steps": 2, "z_every": 2,
+                               "compact_every": 4})
+    sim.step()
+    cnt = sim.counters()
+    dens, cur = sim.int_bins()
+    sim.close()
+    ref = oracle_mod.run(prob)
+    assert np.array_equal(cnt, ref.counters)
+    assert np.array_equal(dens[0], ref.dens[0])
+    assert np.array_equal(cur[0], ref.cur[0])
+    assert ref.dens[0].sum() > 0 and int(cnt[:, 1].sum()) > 10_000  # e-e events took place
