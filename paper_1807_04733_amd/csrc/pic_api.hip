@@ -1142,7 +1142,8 @@ pic_status pic_backward(pic_ctx* c, const double* g_dens, const double* g_cur, d
   if (estimator == 1 && p.off_R < 0)
     return fail(PIC_ESTATE, "whole-tree adjoint needs a context created with adjoint 2 or 3");
   if (estimator != 0 && estimator != 1) return fail(PIC_EINVAL, "estimator must be 0 or 1");
-  drop_graph(c);
+  // the forward's graph stays: the replay enqueues its launches directly and changes
+  // nothing that graph's launches were captured with, so a later forward reuses it
   HIP_TRY(launch_fill32(c->at<uint32_t>(p.off_grad), (int64_t)p.K * 2, 0, c->stream));
   pic_status st;
   if (estimator == 0) {

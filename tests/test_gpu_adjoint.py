@@ -128,3 +128,32 @@ def test_gradient_matches_oracle_batched_tables(torch_gpu, oracle_mod):
     scale = np.abs(ref).max()
     assert g.shape == ref.shape == (4 + 4 * 64,)
     assert np.abs(g - ref).max() <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("estimator", [0, 1])
+def test_forward_after_backward_reuses_its_graph(torch_gpu, oracle_mod, estimator):
+    """Forward (captured as a graph), adjoint replay, then the same forward again from a
+    cleared state and a second replay: the second forward's counters and bins equal the
+    first's and the oracle's, and both gradients equal the oracle's."""
+    from paper_1807_04733_amd import PicSim
+    prob = W.config3(n_primaries=3000, n_steps=60)
+    gd, gc = _random_g(prob, 7)
+    sim = PicSim(prob, adjoint=3, tuning={"block": 512, "grid": 64, "sub_steps": 2,
+                                          "z_every": 4, "compact_every": 8, "use_graph": 1})
+    runs = []
+    for _ in range(2):
+        sim.reset()
+        sim.step()
+        cnt = sim.counters()
+        dens, cur = sim.int_bins()
+        g = sim.backward(gd, gc, estimator)
+        runs.append((cnt, dens[0], cur[0], g))
+    sim.close()
+    ref = oracle_mod.run(prob, g_dens=gd, g_cur=gc, grad_per_tree=estimator == 1)
+    scale = np.abs(ref.grad).max()
+    assert scale > 0
+    for cnt, dens, cur, g in runs:
+        assert np.array_equal(cnt, ref.counters)
+        assert np.array_equal(dens, ref.dens[0])
+        assert np.array_equal(cur, ref.cur[0])
+        assert np.abs(g - ref.grad).max() <= 1e-9 * scale
