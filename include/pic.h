@@ -165,7 +165,7 @@ typedef struct {
 
 /* Launch tuning.  Results never depend on it. */
 typedef struct {
-  int32_t block;          /* threads per workgroup: 64, 128, 256 or 512 */
+  int32_t block;          /* threads per workgroup: 64, 128, 256, 512 or 1024 */
   int32_t grid;           /* persistent workgroups per step launch; 0 = 2 x 256 CUs */
   int32_t compact_every;  /* launch the compaction pass every k steps; 0 = never */
   float   compact_frac;   /* compact a slab when dead slots exceed this fraction */

@@ -1001,8 +1001,8 @@ pic_status pic_reset(pic_ctx* c) {
 pic_status pic_set_tuning(pic_ctx* c, const pic_tuning* t) {
   if (!c || !t) return fail(PIC_EINVAL, "null argument");
   const int b = t->block;
-  if (!(b == 64 || b == 128 || b == 256 || b == 512))
-    return fail(PIC_EINVAL, "block must be 64, 128, 256 or 512");
+  if (!(b == 64 || b == 128 || b == 256 || b == 512 || b == 1024))
+    return fail(PIC_EINVAL, "block must be 64, 128, 256, 512 or 1024");
   if (t->grid < 0 || t->compact_every < 0 || !(t->compact_frac >= 0.0f && t->compact_frac <= 1.0f))
     return fail(PIC_EINVAL, "bad tuning");
   if (t->z_every < 1 || t->z_every > kMaxZEvery) return fail(PIC_EINVAL, "z_every must be 1..8");
@@ -1225,10 +1225,16 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
   }
   pic_tuning cur = c->tune;
   cur.use_graph = 0;
+  // the first stage times two-step launches (stage 3's usual choice), so that the
+  // workgroup size suits the launches that will run: with one-step trials a 1024-thread
+  // workgroup won on the batched workload, whose two-step launches it slows by 4 %
+  cur.sub_steps = kMaxSub;
+  cur.z_every = std::max(cur.z_every, kMaxSub);
   float best_ms = 1e30f;
   pic_tuning win = cur;
-  // stage 1: workgroup size and persistent grid
-  for (int block : {128, 256, 512}) {
+  // stage 1: workgroup size and persistent grid (a 1024-thread workgroup fills a CU alone:
+  // one set of histogram slices per CU, so that LDS holds more queue copies beside them)
+  for (int block : {128, 256, 512, 1024}) {
     if (lds_for(c, block) > c->max_lds) continue;
     for (int grid : {256, 512, 1024, 2048}) {
       pic_tuning t = cur;
@@ -1275,6 +1281,27 @@ pic_status pic_autotune(pic_ctx* c, int32_t trial_steps, pic_tuning* best) {
         pic_tuning t = base;
         t.sub_steps = ns;
         t.z_every = k;
+        float ms = 0;
+        pic_status st = time_trial(c, t, steps2, &ms);
+        if (st != PIC_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          win = t;
+        }
+      }
+    }
+  }
+  // stage 4: the other of the two largest workgroup sizes with the settings chosen so far,
+  // over the longer prefix (which of them wins depends on the histogram slices and queue
+  // copies of the launches that stages 2 and 3 chose)
+  if (win.block == 512 || win.block == 1024) {
+    const pic_tuning base = win;
+    const int other = base.block == 512 ? 1024 : 512;
+    if (lds_for(c, other) <= c->max_lds) {
+      for (int grid : {256, 512, 1024, 2048}) {
+        pic_tuning t = base;
+        t.block = other;
+        t.grid = grid;
         float ms = 0;
         pic_status st = time_trial(c, t, steps2, &ms);
         if (st != PIC_OK) return st;

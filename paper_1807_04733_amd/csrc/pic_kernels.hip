@@ -338,7 +338,7 @@ constexpr int kDynRounds = 16;
 // way.  New primaries (source term, Eq. 17) of a sub-step are appended with their initial
 // state and queued for its general path.
 template <typename F, int T, int MODE>
-__global__ void __launch_bounds__(512, 4) k_step(StepArgs a) {
+__global__ void __launch_bounds__(1024, 4) k_step(StepArgs a) {
   constexpr bool DEBUG = (MODE & kModeDebug) != 0;
   constexpr bool ET = (MODE & kModeTab) != 0;
   constexpr bool RET = (MODE & kModeRet) != 0;      // adjoint pass 1

@@ -120,10 +120,13 @@ def test_gradient_matches_oracle_weighted(torch_gpu, oracle_mod, estimator):
     assert np.abs(g - ref).max() <= 1e-9 * scale
 
 
-def test_gradient_matches_oracle_batched_tables(torch_gpu, oracle_mod):
+@pytest.mark.parametrize("block", [512, 1024])
+def test_gradient_matches_oracle_batched_tables(torch_gpu, oracle_mod, block):
+    """The whole-tree passes in the step kernel, in 512- and 1024-thread workgroups."""
     prob = W.config4(n_instances=2, primaries_per_instance=800, n_steps=300)
     gd, gc = _random_g(prob, 2, frac=0.02)
-    g = _gpu_grad(prob, gd, gc, 1, slab_primaries=300, capacity_factor=30)
+    g = _gpu_grad(prob, gd, gc, 1, slab_primaries=300, capacity_factor=30,
+                  tuning={"block": block, "grid": 8, "sub_steps": 2, "z_every": 4})
     ref = oracle_mod.run(prob, g_dens=gd, g_cur=gc, grad_per_tree=True).grad
     scale = np.abs(ref).max()
     assert g.shape == ref.shape == (4 + 4 * 64,)

@@ -164,7 +164,9 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
                    {"block": 512, "grid": 300, "compact_every": 3, "z_every": 5,
                     "sub_steps": 2},
                    {"block": 256, "grid": 2000, "compact_every": 2, "z_every": 2,
-                    "sub_steps": 2, "use_graph": 0}):
+                    "sub_steps": 2, "use_graph": 0},
+                   {"block": 1024, "grid": 5, "compact_every": 4, "z_every": 4,
+                    "sub_steps": 2}):
         from paper_1807_04733_amd import PicSim
         _say(f"[parity] launch shape {tuning}")
         sim = PicSim(prob, slab_primaries=1000, tuning=tuning)
@@ -180,16 +182,19 @@ def test_results_independent_of_launch_shape(torch_gpu, oracle_mod):
 
 
 @pytest.mark.parametrize("cfg", ["valve", "multilayer"])
-def test_two_step_launches_records(torch_gpu, oracle_mod, cfg):
+@pytest.mark.parametrize("block", [512, 1024])
+def test_two_step_launches_records(torch_gpu, oracle_mod, cfg, block):
     """Two steps per launch (the common path from registers, the general path per
-    sub-step): per-particle records and bins equal the oracle's."""
+    sub-step), in 512- and 1024-thread workgroups (the latter with one set of histogram
+    slices per CU and more queue copies beside them): per-particle records and bins equal
+    the oracle's."""
     if cfg == "valve":
         prob = W.config1(parallel=False, n_primaries=5000, n_steps=121)
     else:
         prob = W.config4(n_instances=2, primaries_per_instance=1200, n_steps=251)
     prob.gen_moment = True
     dev, ref = run_both(prob, oracle_mod, slab_primaries=700,
-                        tuning={"sub_steps": 2, "z_every": 4})
+                        tuning={"sub_steps": 2, "z_every": 4, "block": block, "grid": 16})
     assert_parity(dev, ref, prob)
 
 
@@ -368,7 +373,7 @@ def test_autotune_keeps_results(torch_gpu, oracle_mod):
     sim = PicSim(prob, slab_primaries=600)
     tuned = sim.autotune(trial_steps=20)
     _say(f"[parity] autotuned {tuned}")
-    assert tuned["block"] in (128, 256, 512) and tuned["grid"] > 0
+    assert tuned["block"] in (128, 256, 512, 1024) and tuned["grid"] > 0
     again = sim.autotune(trial_steps=20)          # served from the cache
     assert again == tuned
     sim.step()
